@@ -1,0 +1,231 @@
+"""Benchmark of the 2-D lifting DWT on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = the forward and the inverse transform (one level, CDF 9/7) of one
+8192 x 8192 FP32 image (smooth cosine gradient + Gaussian noise, seeded),
+with inputs resident in HBM, by the fused Monolithic* kernel.  Prints ONE JSON
+line:
+
+  value        Gpixel/s over the timed steps (2 x 8192^2 pixels per step)
+  roofline     the fused forward kernel against the HBM roofline: algorithmic
+               bytes (4 B read + 4 B written per pixel) / its mean duration,
+               timed with HIP events on the launch stream
+  schemes      per-scheme forward / inverse Gpixel/s and % of 8 TB/s
+               (fused Monolithic*, separable Sweldens and row-column, Iwahashi)
+  cpu_baseline the FP64 CPU oracle on the host cores, forward + inverse of the
+               same image
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+BYTES_PER_PX = 8.0             # algorithmic: 4 B read + 4 B written per pixel per level
+WORKLOAD = "cdf97_8192_l1"
+NSETS = 3                      # rotating buffer sets (each 3 x 256 MiB) defeat the 256 MB MALL
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--scheme-reps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU time budget for the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-schemes", action="store_true")
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel_tag: str):
+    """HBM bytes per launch of the dominant kernel from committed PMC counters,
+    or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        import hashlib
+        rec = json.load(open(path))
+        src = os.path.join(ROOT, rec["source"])
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if digest != rec["source_sha256"]:
+            return None
+        return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1605_00561_amd import dwt2, workloads
+
+    dev = torch.device("cuda:0")
+    spec = workloads.WORKLOADS[WORKLOAD]
+    W, H, wav, lev = spec["width"], spec["height"], spec["wavelet"], spec["levels"]
+    img = workloads.workload_image(WORKLOAD)
+    xs = [torch.from_numpy(img).to(dev) for _ in range(NSETS)]
+    ys = [torch.empty_like(xs[0]) for _ in range(NSETS)]
+    zs = [torch.empty_like(xs[0]) for _ in range(NSETS)]
+    stream = torch.cuda.current_stream()
+    npx = W * H
+
+    def step(i, ev=None):
+        k = i % NSETS
+        if ev is not None:
+            ev[0].record(stream)
+        dwt2.forward(xs[k], wav, lev, out=ys[k], scheme="monolithic*")
+        if ev is not None:
+            ev[1].record(stream)
+        dwt2.inverse(ys[k], wav, lev, out=zs[k], scheme="monolithic*")
+        if ev is not None:
+            ev[2].record(stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i, evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    fwd_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    inv_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    value = 2 * npx / (ms_per_step * 1e-3) / 1e9
+
+    fwd_mean = statistics.fmean(fwd_ms)
+    achieved = BYTES_PER_PX * npx / (fwd_mean * 1e-3) / 1e9
+    traffic = traffic_from_profiles("tile_forward_cdf97_mono")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernel": "k_tile_forward<CDF97, MONO_STAR>",
+                "algorithmic_bytes_per_launch": int(BYTES_PER_PX * npx),
+                "mean_launch_us": round(fwd_mean * 1e3, 2),
+                "inverse_mean_launch_us": round(statistics.fmean(inv_ms) * 1e3, 2)}
+
+    # Sanity: the timed output round-trips the input.
+    torch.cuda.synchronize()
+    rt_err = float((zs[(args.steps - 1) % NSETS] - xs[0]).abs().max())
+
+    out = {
+        "metric": "Gpixel/s (2-D DWT, one level, forward + inverse)",
+        "value": round(value, 2), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cdf97_8192x8192_l1_fwd+inv", "wavelet": wav, "width": W,
+                   "height": H, "levels": lev, "scheme": "monolithic*",
+                   "image": "cosine gradient (period 512) + N(0, 8^2), clipped to [0, 255]",
+                   "buffer_sets": NSETS},
+        "roofline": roofline,
+        "round_trip_max_abs": rt_err,
+    }
+
+    if not args.no_schemes:
+        out["schemes"] = scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, args.scheme_reps)
+        out["copy_GBs"] = copy_bandwidth(torch, dev)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(img, wav, lev, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
+    stream = torch.cuda.current_stream()
+    table = {}
+    for scheme in ("monolithic*", "sweldens", "iwahashi", "rowcol"):
+        ws = None
+        st, nbytes = dwt2.dwt2_workspace_bytes(wav, lev, xs[0].shape[1], xs[0].shape[0],
+                                               dwt2.make_options(scheme=scheme))
+        if nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=xs[0].device)
+        res = {}
+        for direction in ("forward", "inverse"):
+            f = dwt2.forward if direction == "forward" else dwt2.inverse
+            src, dst = (xs, ys) if direction == "forward" else (ys, zs)
+            for i in range(2):
+                f(src[i % NSETS], wav, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws)
+            ms = []
+            for i in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                f(src[i % NSETS], wav, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws)
+                e1.record(stream)
+                ms.append((e0, e1))
+            torch.cuda.synchronize()
+            t = statistics.median(a.elapsed_time(b) for a, b in ms)
+            gbs = BYTES_PER_PX * npx / (t * 1e-3) / 1e9
+            res[direction] = {"us": round(t * 1e3, 2), "Gpixel_s": round(npx / (t * 1e-3) / 1e9, 1),
+                              "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        table[scheme] = res
+    return table
+
+
+def copy_bandwidth(torch, dev):
+    n = 64 << 20  # 256 MiB of floats
+    a = torch.empty(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    return round(2 * 4 * n / t / 1e9, 1)
+
+
+def cpu_baseline(img, wav, lev, budget_s):
+    import numpy as np
+
+    import oracle
+
+    x = img.astype(np.float64)
+    threads = oracle.num_threads()
+    t0 = time.perf_counter()
+    y = oracle.forward(x, wav, lev)
+    oracle.inverse(y, wav, lev)
+    one = time.perf_counter() - t0
+    reps = max(1, int(budget_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y = oracle.forward(x, wav, lev)
+        oracle.inverse(y, wav, lev)
+    t = time.perf_counter() - t0
+    npx = x.size
+    return {"value": round(2 * npx * reps / t / 1e9, 4), "unit": "Gpixel/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full {x.shape[1]}x{x.shape[0]} image, forward+inverse, {reps} reps "
+                      f"after 1 warm-up ({t:.1f} s), FP64 C with OpenMP"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,150 @@
+/*
+ * dwt2.h -- C ABI of libdwt2: 2-D forward and inverse discrete wavelet
+ * transform by CDF 5/3 and CDF 9/7 lifting on AMD MI355X (gfx950).
+ *
+ * Method: D. Barina, M. Kula, P. Zemcik, "Parallel Wavelet Schemes for
+ * Images".  One level of the 2-D transform maps each quadruple of input
+ * samples (LL, HL, LH, HH) = (x[2r][2c], x[2r][2c+1], x[2r+1][2c],
+ * x[2r+1][2c+1]) to the four subband coefficients at (r, c) (Sec. 2,
+ * "Convolution and Polyphase Schemes": the 4x4 polyphase matrix N_{P,U}).
+ * Levels are applied in sequence to the LL band (Sec. 1).  The default
+ * scheme is the paper's Monolithic* (Sec. 4, "Improvements"): per lifting
+ * pair one spatial predict step T_{P1} plus the scalar parts T^H_{P0},
+ * T^V_{P0}, and one spatial update step S_{U1} plus S^H_{U0}, S^V_{U0},
+ * separated by two barriers.  Every scheme gives the result of separable
+ * lifting (Conclusions), up to FP32 rounding.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * - Samples are FP32.  Pitches are in ELEMENTS (floats), >= width, as
+ *   torch.Tensor.stride(0).  Pointers are DEVICE pointers, 4-byte aligned.
+ * - Phase: L = x[2n], H = x[2n+1]; a row of width W has ceil(W/2) L and
+ *   floor(W/2) H samples (odd sizes allowed).
+ * - Borders: whole-sample symmetric extension, period 2(N-1) (the paper
+ *   does not fix a border rule; this one keeps the transform of a symmetric
+ *   signal symmetric and needs no extra coefficients).
+ * - Coefficient layout (Mallat): for a W x H level input, LL occupies the
+ *   top-left ceil(H/2) x ceil(W/2) block, HL (horizontal high, vertical low)
+ *   the top-right ceil(H/2) x floor(W/2) block, LH the bottom-left
+ *   floor(H/2) x ceil(W/2) block, HH the bottom-right.  Multi-level output is
+ *   recursive in the LL block.
+ * - Every level's input must be at least 2 x 2: width_k = ceil(W / 2^(k-1))
+ *   and height_k >= 2 for k = 1..levels, else DWT2_E_SIZE.
+ * - Ownership: the caller owns src, dst and workspace.  The library never
+ *   allocates memory and never synchronises: work is enqueued on `stream`
+ *   (0 = the null stream) and completes asynchronously; faults surface at
+ *   the caller's next synchronisation.  src is read only; src and dst must
+ *   not overlap (DWT2_E_ALIAS).  Calls are reentrant; calls that share a
+ *   workspace or dst on different streams race.
+ * - Errors are returned as status codes (no exceptions cross the ABI).
+ *   Arguments are validated on the host before anything is enqueued.
+ */
+#ifndef DWT2_H
+#define DWT2_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DWT2_VERSION 1
+
+/* Status codes. */
+#define DWT2_OK 0
+#define DWT2_E_ARG (-1)         /* null pointer, non-positive size, pitch < width, bad levels */
+#define DWT2_E_SIZE (-2)        /* some level's input is smaller than 2 x 2 */
+#define DWT2_E_UNSUPPORTED (-3) /* unknown wavelet, extension, normalisation or scheme */
+#define DWT2_E_WORKSPACE (-4)   /* workspace missing or smaller than dwt2_workspace_bytes() */
+#define DWT2_E_ALIAS (-5)       /* src and dst (or workspace) overlap */
+#define DWT2_E_HIP (-6)         /* a HIP launch failed; see dwt2_last_hip_error() */
+
+/* Wavelets (Sec. 5, "Evaluation"). */
+typedef enum dwt2_wavelet {
+    DWT2_CDF53 = 0, /* P = -1/2 (1 + z^-1), U = 1/4 (1 + z): one lifting pair */
+    DWT2_CDF97 = 1  /* two lifting pairs alpha, beta, gamma, delta */
+} dwt2_wavelet;
+
+/* Boundary extension.  Only whole-sample symmetric is implemented. */
+typedef enum dwt2_ext { DWT2_EXT_WHOLE_SYMMETRIC = 0 } dwt2_ext;
+
+/*
+ * Normalisation, applied once per 2-D level to LL and HH (HL and LH have
+ * scale 1 in both).  PAPER is the paper's scaling step diag(zeta, 1/zeta)
+ * per axis (Sec. 2; zeta = sqrt(2) for 5/3, 1.14960439886... for 9/7):
+ * LL * zeta^2, HH / zeta^2.  UNIT_DC scales so that a constant image keeps its
+ * value in LL (5/3: no scaling; 9/7: LL / K^2, HH * K^2 with
+ * K = 1.23017410491...).  Per level k the two differ by exact powers of two:
+ * PAPER = UNIT_DC * 2^(k-1) * {2 for LL, 1 for HL and LH, 1/2 for HH}.
+ */
+typedef enum dwt2_norm { DWT2_NORM_UNIT_DC = 0, DWT2_NORM_PAPER = 1 } dwt2_norm;
+
+/*
+ * Scheme of the per-level kernel.  All give the same coefficients up to FP32
+ * rounding (bit-identical for integer input with CDF 5/3).
+ *   MONOLITHIC_STAR  fused tile kernel, 2 barriers per lifting pair (Sec. 4).
+ *   SWELDENS         separable steps T^H_P | T^V_P | S^H_U | S^V_U in the same
+ *                    tile harness, 4 barriers per pair (Sec. 2).
+ *   IWAHASHI         earlier non-separable T^I_P | R^I_{P,U} | S^I_U in the
+ *                    same harness, 3 barriers per pair (Sec. 2).
+ *   ROWCOL           row pass then column pass through device memory.
+ *   AUTO             the fastest implemented scheme (MONOLITHIC_STAR).
+ */
+typedef enum dwt2_scheme {
+    DWT2_SCHEME_AUTO = 0,
+    DWT2_SCHEME_MONOLITHIC_STAR = 1,
+    DWT2_SCHEME_SWELDENS = 2,
+    DWT2_SCHEME_IWAHASHI = 3,
+    DWT2_SCHEME_ROWCOL = 4
+} dwt2_scheme;
+
+/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO). */
+typedef struct dwt2_options {
+    int norm;   /* dwt2_norm */
+    int scheme; /* dwt2_scheme */
+    int reserved[6]; /* must be zero */
+} dwt2_options;
+
+/*
+ * Bytes of device workspace dwt2_forward / dwt2_inverse need for these
+ * arguments (0 when levels == 1 and the scheme needs none).  Writes *bytes.
+ * Returns DWT2_OK or an argument/size/unsupported status.
+ */
+int dwt2_workspace_bytes(dwt2_wavelet wavelet, int levels, int width, int height,
+                         const dwt2_options *opt, size_t *bytes);
+
+/*
+ * Forward transform: src is a width x height image (pitch src_pitch), dst
+ * receives the Mallat layout of `levels` levels (pitch dst_pitch).
+ * workspace: device memory of at least dwt2_workspace_bytes() bytes (may be
+ * NULL when that is 0), not overlapping src or dst.
+ */
+int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int height,
+                 const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
+                 dwt2_ext ext, const dwt2_options *opt, void *workspace,
+                 size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Inverse transform: src holds the Mallat layout produced by dwt2_forward
+ * with the same wavelet, levels, sizes and normalisation; dst receives the
+ * width x height image.  Same argument rules as dwt2_forward.
+ */
+int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int height,
+                 const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
+                 dwt2_ext ext, const dwt2_options *opt, void *workspace,
+                 size_t workspace_bytes, hipStream_t stream);
+
+/* Static text for a status code ("unknown status" for others). */
+const char *dwt2_status_string(int status);
+
+/* hipError_t of the last DWT2_E_HIP returned on the calling thread (0 if none). */
+int dwt2_last_hip_error(void);
+
+/* DWT2_VERSION of the loaded library. */
+int dwt2_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DWT2_H */

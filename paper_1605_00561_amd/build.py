@@ -1,0 +1,78 @@
+"""Build libdwt2.so (HIP, gfx950) in-tree.
+
+    python -m paper_1605_00561_amd.build            # compile changed sources, link
+    python -m paper_1605_00561_amd.build --force    # rebuild everything
+
+Sources are compiled in parallel into _build/ at the repository root and
+linked into paper_1605_00561_amd/libdwt2.so.  Packed FP32 instructions are
+disabled (-Xclang -target-feature -Xclang -packed-fp32-ops).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libdwt2.so")
+ARCH = os.environ.get("DWT2_OFFLOAD_ARCH", "gfx950")
+
+SOURCES = ["dwt2_api.cpp", "tile_kernels.hip", "rowcol_kernels.hip"]
+HEADERS = ["dwt2_internal.h"]
+
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+          "-fvisibility=hidden", "-Wall", "-Wno-unused-function",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-I", INCLUDE, "-I", CSRC]
+
+
+def _newest_dep_mtime() -> float:
+    deps = [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(INCLUDE, "dwt2.h")]
+    return max(os.path.getmtime(d) for d in deps)
+
+
+def _compile(src: str, force: bool) -> str:
+    s = os.path.join(CSRC, src)
+    o = os.path.join(BUILD, src + ".o")
+    if force or not os.path.exists(o) or os.path.getmtime(o) < max(os.path.getmtime(s),
+                                                                    _newest_dep_mtime()):
+        cmd = [HIPCC, *CFLAGS, "-c", s, "-o", o]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        if r.stderr.strip():
+            # the host pass warns that it does not know the packed-fp32 feature
+            lines = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln
+                     and "warning generated" not in ln and ln.strip()]
+            if lines:
+                sys.stderr.write("\n".join(lines) + "\n")
+    return o
+
+
+def build(force: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, force), SOURCES))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--force", action="store_true")
+    args = ap.parse_args()
+    print(build(force=args.force))

@@ -1,0 +1,281 @@
+// dwt2_api.cpp -- host side of the libdwt2 C ABI (declared in include/dwt2.h):
+// argument validation, level geometry, workspace layout and kernel dispatch.
+// Nothing here allocates device memory or synchronises; every launch goes to
+// the caller's stream.
+#include "../../include/dwt2.h"
+
+#include <math.h>
+#include <stdint.h>
+
+#include "dwt2_internal.h"
+
+#define DWT2_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+constexpr int kMaxLevels = 31;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Config {
+    int wavelet, norm, scheme;
+};
+
+int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c)
+{
+    if (wavelet != DWT2_CDF53 && wavelet != DWT2_CDF97) return DWT2_E_UNSUPPORTED;
+    if (ext != DWT2_EXT_WHOLE_SYMMETRIC) return DWT2_E_UNSUPPORTED;
+    c->wavelet = wavelet;
+    c->norm = DWT2_NORM_UNIT_DC;
+    c->scheme = DWT2_SCHEME_AUTO;
+    if (opt) {
+        for (int r : opt->reserved)
+            if (r != 0) return DWT2_E_ARG;
+        c->norm = opt->norm;
+        c->scheme = opt->scheme;
+    }
+    if (c->norm != DWT2_NORM_UNIT_DC && c->norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
+    if (c->scheme < DWT2_SCHEME_AUTO || c->scheme > DWT2_SCHEME_ROWCOL) return DWT2_E_UNSUPPORTED;
+    if (c->scheme == DWT2_SCHEME_AUTO) c->scheme = DWT2_SCHEME_MONOLITHIC_STAR;
+    return DWT2_OK;
+}
+
+// Level k (0-based) transforms a ws[k] x hs[k] block; each must be >= 2 x 2.
+int geometry(int levels, int width, int height, int *ws, int *hs)
+{
+    if (levels < 1 || width < 1 || height < 1) return DWT2_E_ARG;
+    if (levels > kMaxLevels) return DWT2_E_SIZE;
+    int w = width, h = height;
+    for (int k = 0; k < levels; k++) {
+        if (w < 2 || h < 2) return DWT2_E_SIZE;
+        ws[k] = w;
+        hs[k] = h;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    return DWT2_OK;
+}
+
+// Workspace: LL ping-pong buffers A (level-1 LL size) and B (level-2 LL
+// size) when levels > 1, plus a W x H intermediate for the row-column scheme.
+struct Layout {
+    size_t a_off, b_off, t_off, total;
+};
+
+Layout layout(int scheme, int levels, const int *ws, const int *hs)
+{
+    Layout L = {0, 0, 0, 0};
+    size_t off = 0;
+    if (levels >= 2) {
+        L.a_off = off;
+        off += align_up(sizeof(float) * (size_t)((ws[0] + 1) / 2) * (size_t)((hs[0] + 1) / 2));
+    }
+    if (levels >= 3) {
+        L.b_off = off;
+        off += align_up(sizeof(float) * (size_t)((ws[1] + 1) / 2) * (size_t)((hs[1] + 1) / 2));
+    }
+    if (scheme == DWT2_SCHEME_ROWCOL) {
+        L.t_off = off;
+        off += align_up(sizeof(float) * (size_t)ws[0] * (size_t)hs[0]);
+    }
+    L.total = off;
+    return L;
+}
+
+// Per-level scales of LL and HH.  The paper's scaling step diag(zeta, 1/zeta)
+// per axis gives LL * zeta^2 and HH / zeta^2 (HL, LH unscaled).  The unit-DC
+// normalisation divides LL by the squared DC gain K of the unscaled low-pass
+// (K = 1 for 5/3) and multiplies HH by K^2, so PAPER = UNIT_DC * {2, 1/2}
+// exactly, also after rounding to FP32.
+dwt2::Scale level_scale(int wavelet, int norm)
+{
+    double K = 1.0;
+    if (wavelet == DWT2_CDF97) {
+        const double alpha = -1.58613434205992355842832, beta = -0.0529801185729614146241296;
+        K = 1.0 + 2.0 * beta * (1.0 + 2.0 * alpha);  // lifting the constant signal 1
+    }
+    const double ll = 1.0 / (K * K), hh = K * K;
+    dwt2::Scale s;
+    s.ll = (float)(norm == DWT2_NORM_PAPER ? 2.0 * ll : ll);
+    s.hh = (float)(norm == DWT2_NORM_PAPER ? 0.5 * hh : hh);
+    return s;
+}
+
+dwt2::Scale inverse_scale(int wavelet, int norm)
+{
+    const dwt2::Scale s = level_scale(wavelet, norm);
+    dwt2::Scale r;
+    r.ll = (float)(1.0 / (double)s.ll);
+    r.hh = (float)(1.0 / (double)s.hh);
+    return r;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+size_t span_bytes(ptrdiff_t pitch, int w, int h)
+{
+    return sizeof(float) * ((size_t)(h - 1) * (size_t)pitch + (size_t)w);
+}
+
+struct Checked {
+    Config cfg;
+    int ws[kMaxLevels], hs[kMaxLevels];
+    Layout lay;
+};
+
+int check_call(dwt2_wavelet wavelet, int levels, int width, int height, const float *src,
+               ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch, dwt2_ext ext,
+               const dwt2_options *opt, void *workspace, size_t workspace_bytes, Checked *c)
+{
+    int st = parse(wavelet, ext, opt, &c->cfg);
+    if (st != DWT2_OK) return st;
+    st = geometry(levels, width, height, c->ws, c->hs);
+    if (st != DWT2_OK) return st;
+    if (!src || !dst) return DWT2_E_ARG;
+    if (src_pitch < width || dst_pitch < width) return DWT2_E_ARG;
+    if (((uintptr_t)src & 3) || ((uintptr_t)dst & 3)) return DWT2_E_ARG;
+    c->lay = layout(c->cfg.scheme, levels, c->ws, c->hs);
+    if (c->lay.total > 0 && (!workspace || workspace_bytes < c->lay.total)) return DWT2_E_WORKSPACE;
+    if (c->lay.total > 0 && ((uintptr_t)workspace & (kAlign - 1))) return DWT2_E_ARG;
+    const size_t ns = span_bytes(src_pitch, width, height), nd = span_bytes(dst_pitch, width, height);
+    if (overlap(src, ns, dst, nd)) return DWT2_E_ALIAS;
+    if (c->lay.total > 0 &&
+        (overlap(workspace, c->lay.total, src, ns) || overlap(workspace, c->lay.total, dst, nd)))
+        return DWT2_E_ALIAS;
+    return DWT2_OK;
+}
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return DWT2_OK;
+    g_last_hip_error = (int)e;
+    return DWT2_E_HIP;
+}
+
+}  // namespace
+
+DWT2_EXPORT int dwt2_version(void) { return DWT2_VERSION; }
+
+DWT2_EXPORT int dwt2_last_hip_error(void) { return g_last_hip_error; }
+
+DWT2_EXPORT const char *dwt2_status_string(int status)
+{
+    switch (status) {
+    case DWT2_OK: return "ok";
+    case DWT2_E_ARG: return "invalid argument";
+    case DWT2_E_SIZE: return "a level's input is smaller than 2x2";
+    case DWT2_E_UNSUPPORTED: return "unsupported wavelet, extension, normalisation or scheme";
+    case DWT2_E_WORKSPACE: return "workspace missing or too small";
+    case DWT2_E_ALIAS: return "src, dst or workspace overlap";
+    case DWT2_E_HIP: return "HIP launch failed";
+    default: return "unknown status";
+    }
+}
+
+DWT2_EXPORT int dwt2_workspace_bytes(dwt2_wavelet wavelet, int levels, int width, int height,
+                                     const dwt2_options *opt, size_t *bytes)
+{
+    Config cfg;
+    int ws[kMaxLevels], hs[kMaxLevels];
+    if (!bytes) return DWT2_E_ARG;
+    int st = parse(wavelet, DWT2_EXT_WHOLE_SYMMETRIC, opt, &cfg);
+    if (st != DWT2_OK) return st;
+    st = geometry(levels, width, height, ws, hs);
+    if (st != DWT2_OK) return st;
+    *bytes = layout(cfg.scheme, levels, ws, hs).total;
+    return DWT2_OK;
+}
+
+DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int height,
+                             const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
+                             dwt2_ext ext, const dwt2_options *opt, void *workspace,
+                             size_t workspace_bytes, hipStream_t stream)
+{
+    Checked c;
+    int st = check_call(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext, opt,
+                        workspace, workspace_bytes, &c);
+    if (st != DWT2_OK) return st;
+    char *wsb = (char *)workspace;
+    float *buf[2] = {(float *)(wsb + c.lay.a_off), (float *)(wsb + c.lay.b_off)};
+    float *tmp = (float *)(wsb + c.lay.t_off);
+    const dwt2::Scale s = level_scale(c.cfg.wavelet, c.cfg.norm);
+    const float *in = src;
+    ptrdiff_t in_pitch = src_pitch;
+    for (int k = 0; k < levels; k++) {
+        const int W = c.ws[k], H = c.hs[k];
+        dwt2::FwdArgs a;
+        a.in = in;
+        a.in_pitch = in_pitch;
+        a.det = dst;
+        a.det_pitch = dst_pitch;
+        a.W = W;
+        a.H = H;
+        a.s = s;
+        if (k == levels - 1) {
+            a.ll = dst;
+            a.ll_pitch = dst_pitch;
+        } else {  // level k+1 (1-based) writes its LL to buffer A if odd, B if even
+            a.ll = buf[k & 1];
+            a.ll_pitch = (W + 1) / 2;
+        }
+        hipError_t e = c.cfg.scheme == DWT2_SCHEME_ROWCOL
+                           ? dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, W, stream)
+                           : dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
+        if (e != hipSuccess) return hip_status(e);
+        in = a.ll;
+        in_pitch = a.ll_pitch;
+    }
+    return DWT2_OK;
+}
+
+DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int height,
+                             const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
+                             dwt2_ext ext, const dwt2_options *opt, void *workspace,
+                             size_t workspace_bytes, hipStream_t stream)
+{
+    Checked c;
+    int st = check_call(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext, opt,
+                        workspace, workspace_bytes, &c);
+    if (st != DWT2_OK) return st;
+    char *wsb = (char *)workspace;
+    float *buf[2] = {(float *)(wsb + c.lay.a_off), (float *)(wsb + c.lay.b_off)};
+    float *tmp = (float *)(wsb + c.lay.t_off);
+    const dwt2::Scale r = inverse_scale(c.cfg.wavelet, c.cfg.norm);
+    // Level k (0-based) reconstructs its W_k x H_k input from LL_{k+1} and
+    // the details in src.  LL_j (1-based j) lives in buffer A for odd j, B
+    // for even j, exactly as in the forward direction.
+    const float *ll = src;
+    ptrdiff_t ll_pitch = src_pitch;
+    for (int k = levels - 1; k >= 0; k--) {
+        const int W = c.ws[k], H = c.hs[k];
+        dwt2::InvArgs a;
+        a.ll = ll;
+        a.ll_pitch = ll_pitch;
+        a.det = src;
+        a.det_pitch = src_pitch;
+        a.W = W;
+        a.H = H;
+        a.inv_s = r;
+        if (k == 0) {
+            a.out = dst;
+            a.out_pitch = dst_pitch;
+        } else {  // output is LL_k (1-based k): buffer A if k odd, B if even
+            a.out = buf[(k - 1) & 1];
+            a.out_pitch = W;
+        }
+        hipError_t e = c.cfg.scheme == DWT2_SCHEME_ROWCOL
+                           ? dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, W, stream)
+                           : dwt2::launch_tile_inverse(c.cfg.wavelet, c.cfg.scheme, a, stream);
+        if (e != hipSuccess) return hip_status(e);
+        ll = a.out;
+        ll_pitch = a.out_pitch;
+    }
+    return DWT2_OK;
+}

@@ -1,0 +1,106 @@
+// dwt2_internal.h -- shared declarations of the libdwt2 kernels and host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dwt2 {
+
+enum Wavelet : int { CDF53 = 0, CDF97 = 1 };
+enum Scheme : int { MONO_STAR = 1, SWELDENS = 2, IWAHASHI = 3, ROWCOL = 4 };
+
+// Lifting pairs in the L = x[2n], H = x[2n+1] phase.  The paper's operators
+// (Sec. 5) P(z) = p (1 + z^-1) and U(z) = u (1 + z) become, after the index
+// relabelling of H, P = p (1 + z) (predict H[n] from L[n], L[n+1]) and
+// U = u (1 + z^-1) (update L[n] from H[n-1], H[n]).  The scalar part of each
+// operator (Sec. 4's P0, U0) is p resp. u; the neighbour part (P1, U1) is
+// p z resp. u z^-1.
+//
+// CDF 9/7 values (not printed in the paper): alpha..delta follow from
+// factoring the 4-vanishing-moment CDF filters built on the real root of
+// 1 + 4y + 10y^2 + 20y^3; K is the DC gain of the unscaled low-pass and
+// zeta = sqrt(2) / K the paper's scaling factor.
+template <int W>
+struct Lift;
+
+template <>
+struct Lift<CDF53> {
+    static constexpr int K = 1;  // lifting pairs
+    __host__ __device__ static constexpr float p(int) { return -0.5f; }
+    __host__ __device__ static constexpr float u(int) { return 0.25f; }
+};
+
+template <>
+struct Lift<CDF97> {
+    static constexpr int K = 2;
+    __host__ __device__ static constexpr float p(int k)
+    {
+        return k == 0 ? -1.58613434205992355842832f : 0.88291107553093329591979f;
+    }
+    __host__ __device__ static constexpr float u(int k)
+    {
+        return k == 0 ? -0.0529801185729614146241296f : 0.443506852043971152115604f;
+    }
+};
+
+// Per-level scale of LL and HH (HL and LH are unscaled in both normalisations).
+struct Scale {
+    float ll, hh;
+};
+
+// Whole-sample symmetric extension: index j -> [0, n), period 2(n-1), n >= 2.
+__host__ __device__ __forceinline__ int ws_mirror(int j, int n)
+{
+    if ((unsigned)j < (unsigned)n) return j;
+    const int p = 2 * (n - 1);
+    j %= p;
+    if (j < 0) j += p;
+    return j >= n ? p - j : j;
+}
+
+// One forward level: `in` (W x H) -> LL into `ll`, HL/LH/HH into the Mallat
+// positions of `det` (HL at column ceil(W/2), LH at row ceil(H/2)).
+struct FwdArgs {
+    const float *in;
+    ptrdiff_t in_pitch;
+    float *ll;
+    ptrdiff_t ll_pitch;
+    float *det;
+    ptrdiff_t det_pitch;
+    int W, H;
+    Scale s;
+};
+
+// One inverse level: LL from `ll`, HL/LH/HH from `det` -> `out` (W x H).
+struct InvArgs {
+    const float *ll;
+    ptrdiff_t ll_pitch;
+    const float *det;
+    ptrdiff_t det_pitch;
+    float *out;
+    ptrdiff_t out_pitch;
+    int W, H;
+    Scale inv_s;  // reciprocal scales
+};
+
+// Launch `kern` and return the status of this launch only (hipLaunchKernel
+// does not report errors left behind by earlier, unrelated HIP calls).
+template <typename... Args>
+inline hipError_t launch(void (*kern)(Args...), dim3 grid, dim3 block, hipStream_t s, Args... args)
+{
+    void *argv[] = {(void *)&args...};
+    return hipLaunchKernel((const void *)kern, grid, block, argv, 0, s);
+}
+
+// Launchers (return the hipError_t of the launch).
+hipError_t launch_tile_forward(int wavelet, int scheme, const FwdArgs &a, hipStream_t s);
+hipError_t launch_tile_inverse(int wavelet, int scheme, const InvArgs &a, hipStream_t s);
+
+// Row-column: the intermediate `tmp` is W x H with pitch tmp_pitch.
+hipError_t launch_rowcol_forward(int wavelet, const FwdArgs &a, float *tmp, ptrdiff_t tmp_pitch,
+                                 hipStream_t s);
+hipError_t launch_rowcol_inverse(int wavelet, const InvArgs &a, float *tmp, ptrdiff_t tmp_pitch,
+                                 hipStream_t s);
+
+}  // namespace dwt2

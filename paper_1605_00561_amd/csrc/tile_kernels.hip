@@ -1,0 +1,522 @@
+// tile_kernels.hip -- block-based 2-D lifting kernels: one launch per level.
+//
+// Mapping (Sec. 6, "Performance"): each work-group owns one overlapping tile
+// of TX x TY quadruples (including a halo of K quadruples per side, K = the
+// number of lifting pairs), one thread per quadruple column and TY / 4 rows
+// per thread.  A thread keeps its quadruples in registers; LDS only carries
+// the components that neighbouring threads read in the next spatial step.
+// Two LDS buffers alternate between consecutive steps (the paper's "double
+// buffering", Table 2), so every step that reads a neighbour costs exactly
+// one barrier:
+//
+//   Monolithic*  (Sec. 4)  T_{P1}+T^H_{P0}+T^V_{P0} | S_{U1}+S^H_{U0}+S^V_{U0}
+//                          2 barriers per pair, 6 LDS cells per quadruple
+//   Sweldens     (Sec. 2)  T^H_P | T^V_P | S^H_U | S^V_U
+//                          4 barriers per pair, 4 LDS cells
+//   Iwahashi     (Sec. 2)  T^I_P | R^I_{P,U} | S^I_U
+//                          3 barriers per pair, 6 LDS cells
+//
+// Operators in the L = x[2n] phase (see dwt2_internal.h): for a component
+// X at quadruple (r, c), P X = p (X + X[r][c+1]), P* X = p (X + X[r+1][c]),
+// U X = u (X + X[r][c-1]), U* X = u (X + X[r-1][c]).
+//
+// The tile is computed on the whole-sample symmetric extension of the
+// image: every halo sample is read from its mirrored position, and lifting
+// steps preserve that symmetry, so interior results equal per-step index
+// mirroring.  After pair k only quadruples at least k+1 from the tile edge
+// are valid; the interior (TX - 2K) x (TY - 2K) quadruples are stored.
+//
+// Work-groups are numbered so that each of the 8 XCDs (workgroup id mod 8)
+// receives a contiguous run of tiles in row-major order, so the halo rows
+// and columns shared by neighbouring tiles are re-read from the same L2.
+#include "dwt2_internal.h"
+
+namespace dwt2 {
+namespace {
+
+constexpr int TX = 64;  // quadruple columns per tile = wavefront size
+constexpr int NWAVES = 4;
+constexpr int NTHREADS = TX * NWAVES;
+constexpr int TY = 28;  // quadruple rows per tile (incl. halo)
+constexpr int NJ = TY / NWAVES;
+constexpr int PS = TX + 2;               // padded plane row stride
+constexpr int PSZ = (TY + 2) * PS;       // padded plane size (1 cell each side)
+
+enum { LL = 0, HL = 1, LH = 2, HH = 3 };
+
+__device__ __forceinline__ int xcd_tile(int ntiles)
+{
+    const int per = gridDim.x >> 3;  // grid is a multiple of 8
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    return t < ntiles ? t : -1;
+}
+
+// LDS access: plane `pl`, tile row r, tile column c; r in [-1, TY], c in [-1, TX].
+__device__ __forceinline__ float &cell(float *lds, int pl, int r, int c)
+{
+    return lds[pl * PSZ + (r + 1) * PS + (c + 1)];
+}
+
+struct Quads {
+    float v[NJ][4];
+};
+
+template <int C>
+__device__ __forceinline__ void publish(float *lds, int pl, const Quads &q, int lane, int wv)
+{
+#pragma unroll
+    for (int j = 0; j < NJ; j++) cell(lds, pl, j * NWAVES + wv, lane) = q.v[j][C];
+}
+
+// ---------------------------------------------------------------------------
+// Monolithic* steps.  Neighbour parts read pre-step values from LDS; the
+// scalar parts follow in the order T^H then T^V (S^H then S^V).  The four
+// factors of each step commute (Sec. 4), so this order is exact algebra.
+// ---------------------------------------------------------------------------
+template <bool INV>
+__device__ __forceinline__ void mono_predict(float *lds, int A, Quads &q, int lane, int wv, float p)
+{
+    const float p2 = p * p;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float llr = cell(lds, A + 0, r, lane + 1);
+        const float lld = cell(lds, A + 0, r + 1, lane);
+        const float lldr = cell(lds, A + 0, r + 1, lane + 1);
+        const float hld = cell(lds, A + 1, r + 1, lane);
+        const float lhr = cell(lds, A + 2, r, lane + 1);
+        float &ll = q.v[j][LL], &hl = q.v[j][HL], &lh = q.v[j][LH], &hh = q.v[j][HH];
+        if (!INV) {
+            // T_{P1}: HL += p LL[c+1]; LH += p LL[r+1]; HH += p^2 LL[r+1][c+1] + p HL[r+1] + p LH[c+1]
+            hl = fmaf(p, llr, hl);
+            lh = fmaf(p, lld, lh);
+            hh = fmaf(p2, lldr, fmaf(p, hld, fmaf(p, lhr, hh)));
+            // T^H_{P0}: HL += p LL; HH += p LH.  T^V_{P0}: LH += p LL; HH += p HL.
+            hl = fmaf(p, ll, hl);
+            hh = fmaf(p, lh, hh);
+            lh = fmaf(p, ll, lh);
+            hh = fmaf(p, hl, hh);
+        } else {
+            // T_{-P1} (the scalar parts were undone before the publish)
+            hl = fmaf(-p, llr, hl);
+            lh = fmaf(-p, lld, lh);
+            hh = fmaf(p2, lldr, fmaf(-p, hld, fmaf(-p, lhr, hh)));
+        }
+    }
+}
+
+template <bool INV>
+__device__ __forceinline__ void mono_update(float *lds, int B, Quads &q, int lane, int wv, float u)
+{
+    const float u2 = u * u;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float hll = cell(lds, B + 0, r, lane - 1);
+        const float lhu = cell(lds, B + 1, r - 1, lane);
+        const float hhul = cell(lds, B + 2, r - 1, lane - 1);
+        const float hhu = cell(lds, B + 2, r - 1, lane);
+        const float hhl = cell(lds, B + 2, r, lane - 1);
+        float &ll = q.v[j][LL], &hl = q.v[j][HL], &lh = q.v[j][LH], &hh = q.v[j][HH];
+        if (!INV) {
+            // S_{U1}: LL += u HL[c-1] + u LH[r-1] + u^2 HH[r-1][c-1]; HL += u HH[r-1]; LH += u HH[c-1]
+            ll = fmaf(u, hll, fmaf(u, lhu, fmaf(u2, hhul, ll)));
+            hl = fmaf(u, hhu, hl);
+            lh = fmaf(u, hhl, lh);
+            // S^H_{U0}: LL += u HL; LH += u HH.  S^V_{U0}: LL += u LH; HL += u HH.
+            ll = fmaf(u, hl, ll);
+            lh = fmaf(u, hh, lh);
+            ll = fmaf(u, lh, ll);
+            hl = fmaf(u, hh, hl);
+        } else {
+            // S_{-U1}: LL += -u HL[c-1] - u LH[r-1] + u^2 HH[r-1][c-1]; HL -= u HH[r-1]; LH -= u HH[c-1]
+            ll = fmaf(-u, hll, fmaf(-u, lhu, fmaf(u2, hhul, ll)));
+            hl = fmaf(-u, hhu, hl);
+            lh = fmaf(-u, hhl, lh);
+        }
+    }
+}
+
+// Inverse of the scalar parts, applied before the neighbour step.
+__device__ __forceinline__ void mono_unupdate_local(Quads &q, float u)
+{
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        float &ll = q.v[j][LL], &hl = q.v[j][HL], &lh = q.v[j][LH], &hh = q.v[j][HH];
+        ll = fmaf(-u, lh, ll);  // undo S^V_{U0}
+        hl = fmaf(-u, hh, hl);
+        ll = fmaf(-u, hl, ll);  // undo S^H_{U0}
+        lh = fmaf(-u, hh, lh);
+    }
+}
+
+__device__ __forceinline__ void mono_unpredict_local(Quads &q, float p)
+{
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        float &ll = q.v[j][LL], &hl = q.v[j][HL], &lh = q.v[j][LH], &hh = q.v[j][HH];
+        hh = fmaf(-p, hl, hh);  // undo T^V_{P0}
+        lh = fmaf(-p, ll, lh);
+        hh = fmaf(-p, lh, hh);  // undo T^H_{P0}
+        hl = fmaf(-p, ll, hl);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sweldens steps (separable, one direction per step).  s = +1 forward, -1 inverse.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void swel_TH(float *lds, int A, Quads &q, int lane, int wv, float p)
+{   // HL += P LL; HH += P LH       (reads LL, LH at c+1)
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        q.v[j][HL] = fmaf(p, q.v[j][LL] + cell(lds, A + 0, r, lane + 1), q.v[j][HL]);
+        q.v[j][HH] = fmaf(p, q.v[j][LH] + cell(lds, A + 1, r, lane + 1), q.v[j][HH]);
+    }
+}
+__device__ __forceinline__ void swel_TV(float *lds, int A, Quads &q, int lane, int wv, float p)
+{   // LH += P* LL; HH += P* HL     (reads LL, HL at r+1)
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        q.v[j][LH] = fmaf(p, q.v[j][LL] + cell(lds, A + 0, r + 1, lane), q.v[j][LH]);
+        q.v[j][HH] = fmaf(p, q.v[j][HL] + cell(lds, A + 1, r + 1, lane), q.v[j][HH]);
+    }
+}
+__device__ __forceinline__ void swel_SH(float *lds, int A, Quads &q, int lane, int wv, float u)
+{   // LL += U HL; LH += U HH       (reads HL, HH at c-1)
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        q.v[j][LL] = fmaf(u, q.v[j][HL] + cell(lds, A + 0, r, lane - 1), q.v[j][LL]);
+        q.v[j][LH] = fmaf(u, q.v[j][HH] + cell(lds, A + 1, r, lane - 1), q.v[j][LH]);
+    }
+}
+__device__ __forceinline__ void swel_SV(float *lds, int A, Quads &q, int lane, int wv, float u)
+{   // LL += U* LH; HL += U* HH     (reads LH, HH at r-1)
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        q.v[j][LL] = fmaf(u, q.v[j][LH] + cell(lds, A + 0, r - 1, lane), q.v[j][LL]);
+        q.v[j][HL] = fmaf(u, q.v[j][HH] + cell(lds, A + 1, r - 1, lane), q.v[j][HL]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Iwahashi steps (non-separable, three per pair).  sg = +1 forward, -1 inverse:
+// the inverse of each step subtracts the same terms (each reads components the
+// step does not modify), except that the product terms keep their sign rule.
+// ---------------------------------------------------------------------------
+template <bool INV>
+__device__ __forceinline__ void iwa_T(float *lds, int A, Quads &q, int lane, int wv, float p)
+{   // HH += P P* LL + P* HL + P LH   (reads LL at c+1, r+1, (r+1,c+1); HL at r+1; LH at c+1)
+    const float sp = INV ? -p : p;
+    const float sp2 = INV ? -(p * p) : p * p;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float llsum = (q.v[j][LL] + cell(lds, A + 0, r, lane + 1)) +
+                            (cell(lds, A + 0, r + 1, lane) + cell(lds, A + 0, r + 1, lane + 1));
+        float hh = q.v[j][HH];
+        hh = fmaf(sp, q.v[j][LH] + cell(lds, A + 2, r, lane + 1), hh);
+        hh = fmaf(sp, q.v[j][HL] + cell(lds, A + 1, r + 1, lane), hh);
+        q.v[j][HH] = fmaf(sp2, llsum, hh);
+    }
+}
+template <bool INV>
+__device__ __forceinline__ void iwa_R(float *lds, int B, Quads &q, int lane, int wv, float p, float u)
+{   // HL += P LL + U* HH; LH += P* LL + U HH   (reads LL at c+1, r+1; HH at r-1, c-1)
+    const float sp = INV ? -p : p;
+    const float su = INV ? -u : u;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float ll = q.v[j][LL], hh = q.v[j][HH];
+        q.v[j][HL] = fmaf(su, hh + cell(lds, B + 1, r - 1, lane),
+                          fmaf(sp, ll + cell(lds, B + 0, r, lane + 1), q.v[j][HL]));
+        q.v[j][LH] = fmaf(su, hh + cell(lds, B + 1, r, lane - 1),
+                          fmaf(sp, ll + cell(lds, B + 0, r + 1, lane), q.v[j][LH]));
+    }
+}
+template <bool INV>
+__device__ __forceinline__ void iwa_S(float *lds, int A, Quads &q, int lane, int wv, float u)
+{   // LL += U HL + U* LH - U U* HH   (reads HL at c-1; LH at r-1; HH at c-1, r-1, (r-1,c-1))
+    const float su = INV ? -u : u;
+    const float su2 = INV ? (u * u) : -(u * u);
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float hhsum = (q.v[j][HH] + cell(lds, A + 2, r, lane - 1)) +
+                            (cell(lds, A + 2, r - 1, lane) + cell(lds, A + 2, r - 1, lane - 1));
+        float ll = q.v[j][LL];
+        ll = fmaf(su, q.v[j][HL] + cell(lds, A + 0, r, lane - 1), ll);
+        ll = fmaf(su, q.v[j][LH] + cell(lds, A + 1, r - 1, lane), ll);
+        q.v[j][LL] = fmaf(su2, hhsum, ll);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The transform of one tile held in registers.  `step` counts spatial steps so
+// that consecutive steps use alternating LDS buffers.
+// ---------------------------------------------------------------------------
+template <int WAV, int SCH, bool INV>
+__device__ __forceinline__ void transform_tile(float *lds, Quads &q, int lane, int wv)
+{
+    using L = Lift<WAV>;
+    constexpr int BUF = (SCH == SWELDENS) ? 2 : 3;  // planes per buffer
+    int step = 0;
+    auto buf = [&]() { return (step++ & 1) * BUF; };
+#define SYNC() __syncthreads()
+    if constexpr (SCH == MONO_STAR) {
+#pragma unroll
+        for (int kk = 0; kk < L::K; kk++) {
+            const int k = INV ? L::K - 1 - kk : kk;
+            const float p = L::p(k), u = L::u(k);
+            if (!INV) {
+                int A = buf();
+                publish<LL>(lds, A + 0, q, lane, wv);
+                publish<HL>(lds, A + 1, q, lane, wv);
+                publish<LH>(lds, A + 2, q, lane, wv);
+                SYNC();
+                mono_predict<false>(lds, A, q, lane, wv, p);
+                int B = buf();
+                publish<HL>(lds, B + 0, q, lane, wv);
+                publish<LH>(lds, B + 1, q, lane, wv);
+                publish<HH>(lds, B + 2, q, lane, wv);
+                SYNC();
+                mono_update<false>(lds, B, q, lane, wv, u);
+            } else {
+                mono_unupdate_local(q, u);
+                int B = buf();
+                publish<HL>(lds, B + 0, q, lane, wv);
+                publish<LH>(lds, B + 1, q, lane, wv);
+                publish<HH>(lds, B + 2, q, lane, wv);
+                SYNC();
+                mono_update<true>(lds, B, q, lane, wv, u);
+                mono_unpredict_local(q, p);
+                int A = buf();
+                publish<LL>(lds, A + 0, q, lane, wv);
+                publish<HL>(lds, A + 1, q, lane, wv);
+                publish<LH>(lds, A + 2, q, lane, wv);
+                SYNC();
+                mono_predict<true>(lds, A, q, lane, wv, p);
+            }
+        }
+    } else if constexpr (SCH == SWELDENS) {
+#pragma unroll
+        for (int kk = 0; kk < L::K; kk++) {
+            const int k = INV ? L::K - 1 - kk : kk;
+            const float p = L::p(k), u = L::u(k);
+            int A;
+            if (!INV) {
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                SYNC(); swel_TH(lds, A, q, lane, wv, p);
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+                SYNC(); swel_TV(lds, A, q, lane, wv, p);
+                A = buf(); publish<HL>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
+                SYNC(); swel_SH(lds, A, q, lane, wv, u);
+                A = buf(); publish<LH>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
+                SYNC(); swel_SV(lds, A, q, lane, wv, u);
+            } else {
+                A = buf(); publish<LH>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
+                SYNC(); swel_SV(lds, A, q, lane, wv, -u);
+                A = buf(); publish<HL>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
+                SYNC(); swel_SH(lds, A, q, lane, wv, -u);
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+                SYNC(); swel_TV(lds, A, q, lane, wv, -p);
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                SYNC(); swel_TH(lds, A, q, lane, wv, -p);
+            }
+        }
+    } else if constexpr (SCH == IWAHASHI) {
+#pragma unroll
+        for (int kk = 0; kk < L::K; kk++) {
+            const int k = INV ? L::K - 1 - kk : kk;
+            const float p = L::p(k), u = L::u(k);
+            int A;
+            if (!INV) {
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+                publish<LH>(lds, A + 2, q, lane, wv);
+                SYNC(); iwa_T<false>(lds, A, q, lane, wv, p);
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
+                SYNC(); iwa_R<false>(lds, A, q, lane, wv, p, u);
+                A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                publish<HH>(lds, A + 2, q, lane, wv);
+                SYNC(); iwa_S<false>(lds, A, q, lane, wv, u);
+            } else {
+                A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                publish<HH>(lds, A + 2, q, lane, wv);
+                SYNC(); iwa_S<true>(lds, A, q, lane, wv, u);
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
+                SYNC(); iwa_R<true>(lds, A, q, lane, wv, p, u);
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+                publish<LH>(lds, A + 2, q, lane, wv);
+                SYNC(); iwa_T<true>(lds, A, q, lane, wv, p);
+            }
+        }
+    }
+#undef SYNC
+}
+
+template <int SCH>
+constexpr int lds_planes() { return SCH == SWELDENS ? 4 : 6; }
+
+template <int WAV, int SCH>
+__global__ __launch_bounds__(NTHREADS) void k_tile_forward(FwdArgs a, int ntx, int ntiles)
+{
+    constexpr int HQ = Lift<WAV>::K;
+    constexpr int IX = TX - 2 * HQ, IY = TY - 2 * HQ;
+    __shared__ float lds[lds_planes<SCH>() * PSZ];
+    const int tile = xcd_tile(ntiles);
+    if (tile < 0) return;
+    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+    const int tc = tile % ntx, tr = tile / ntx;
+    const int W = a.W, H = a.H;
+    const int QW = (W + 1) >> 1, QH = (H + 1) >> 1, WH = W >> 1, HH_ = H >> 1;
+    const int qc = tc * IX - HQ + lane;
+    const int x0 = ws_mirror(2 * qc, W), x1 = ws_mirror(2 * qc + 1, W);
+
+    Quads q;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int qr = tr * IY - HQ + j * NWAVES + wv;
+        const float *r0 = a.in + (ptrdiff_t)ws_mirror(2 * qr, H) * a.in_pitch;
+        const float *r1 = a.in + (ptrdiff_t)ws_mirror(2 * qr + 1, H) * a.in_pitch;
+        q.v[j][LL] = r0[x0];
+        q.v[j][HL] = r0[x1];
+        q.v[j][LH] = r1[x0];
+        q.v[j][HH] = r1[x1];
+    }
+
+    transform_tile<WAV, SCH, false>(lds, q, lane, wv);
+
+    if (lane < HQ || lane >= TX - HQ || qc >= QW) return;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const int qr = tr * IY - HQ + r;
+        if (r < HQ || r >= TY - HQ || qr >= QH) continue;
+        a.ll[(ptrdiff_t)qr * a.ll_pitch + qc] = q.v[j][LL] * a.s.ll;
+        float *drow = a.det + (ptrdiff_t)qr * a.det_pitch;
+        if (qc < WH) drow[QW + qc] = q.v[j][HL];
+        if (qr < HH_) {
+            float *hrow = a.det + (ptrdiff_t)(QH + qr) * a.det_pitch;
+            hrow[qc] = q.v[j][LH];
+            if (qc < WH) hrow[QW + qc] = q.v[j][HH] * a.s.hh;
+        }
+    }
+}
+
+template <int WAV, int SCH>
+__global__ __launch_bounds__(NTHREADS) void k_tile_inverse(InvArgs a, int ntx, int ntiles)
+{
+    constexpr int HQ = Lift<WAV>::K;
+    constexpr int IX = TX - 2 * HQ, IY = TY - 2 * HQ;
+    __shared__ float lds[lds_planes<SCH>() * PSZ];
+    const int tile = xcd_tile(ntiles);
+    if (tile < 0) return;
+    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+    const int tc = tile % ntx, tr = tile / ntx;
+    const int W = a.W, H = a.H;
+    const int QW = (W + 1) >> 1, QH = (H + 1) >> 1;
+    const int qc = tc * IX - HQ + lane;
+    // Coefficient columns of the mirrored L and H samples (mirroring keeps parity).
+    const int cl = ws_mirror(2 * qc, W) >> 1, ch = ws_mirror(2 * qc + 1, W) >> 1;
+
+    Quads q;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int qr = tr * IY - HQ + j * NWAVES + wv;
+        const int rl = ws_mirror(2 * qr, H) >> 1, rh = ws_mirror(2 * qr + 1, H) >> 1;
+        const float *lrow = a.det + (ptrdiff_t)rl * a.det_pitch;
+        const float *hrow = a.det + (ptrdiff_t)(QH + rh) * a.det_pitch;
+        q.v[j][LL] = a.ll[(ptrdiff_t)rl * a.ll_pitch + cl] * a.inv_s.ll;
+        q.v[j][HL] = lrow[QW + ch];
+        q.v[j][LH] = hrow[cl];
+        q.v[j][HH] = hrow[QW + ch] * a.inv_s.hh;
+    }
+
+    transform_tile<WAV, SCH, true>(lds, q, lane, wv);
+
+    if (lane < HQ || lane >= TX - HQ || qc >= QW) return;
+    const int px = 2 * qc;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const int qr = tr * IY - HQ + r;
+        if (r < HQ || r >= TY - HQ || qr >= QH) continue;
+        const int py = 2 * qr;
+        float *o0 = a.out + (ptrdiff_t)py * a.out_pitch;
+        o0[px] = q.v[j][LL];
+        if (px + 1 < W) o0[px + 1] = q.v[j][HL];
+        if (py + 1 < H) {
+            float *o1 = o0 + a.out_pitch;
+            o1[px] = q.v[j][LH];
+            if (px + 1 < W) o1[px + 1] = q.v[j][HH];
+        }
+    }
+}
+
+struct Grid {
+    int ntx, ntiles, blocks;
+};
+
+template <int WAV>
+Grid tile_grid(int W, int H)
+{
+    constexpr int HQ = Lift<WAV>::K;
+    const int QW = (W + 1) / 2, QH = (H + 1) / 2;
+    const int ix = TX - 2 * HQ, iy = TY - 2 * HQ;
+    Grid g;
+    g.ntx = (QW + ix - 1) / ix;
+    const int nty = (QH + iy - 1) / iy;
+    g.ntiles = g.ntx * nty;
+    g.blocks = (g.ntiles + 7) / 8 * 8;
+    return g;
+}
+
+template <int WAV, int SCH>
+hipError_t fwd(const FwdArgs &a, hipStream_t s)
+{
+    const Grid g = tile_grid<WAV>(a.W, a.H);
+    return launch(k_tile_forward<WAV, SCH>, dim3(g.blocks), dim3(NTHREADS), s, a, g.ntx, g.ntiles);
+}
+
+template <int WAV, int SCH>
+hipError_t inv(const InvArgs &a, hipStream_t s)
+{
+    const Grid g = tile_grid<WAV>(a.W, a.H);
+    return launch(k_tile_inverse<WAV, SCH>, dim3(g.blocks), dim3(NTHREADS), s, a, g.ntx, g.ntiles);
+}
+
+}  // namespace
+
+hipError_t launch_tile_forward(int wavelet, int scheme, const FwdArgs &a, hipStream_t s)
+{
+    if (wavelet == CDF53) {
+        if (scheme == MONO_STAR) return fwd<CDF53, MONO_STAR>(a, s);
+        if (scheme == SWELDENS) return fwd<CDF53, SWELDENS>(a, s);
+        if (scheme == IWAHASHI) return fwd<CDF53, IWAHASHI>(a, s);
+    } else if (wavelet == CDF97) {
+        if (scheme == MONO_STAR) return fwd<CDF97, MONO_STAR>(a, s);
+        if (scheme == SWELDENS) return fwd<CDF97, SWELDENS>(a, s);
+        if (scheme == IWAHASHI) return fwd<CDF97, IWAHASHI>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tile_inverse(int wavelet, int scheme, const InvArgs &a, hipStream_t s)
+{
+    if (wavelet == CDF53) {
+        if (scheme == MONO_STAR) return inv<CDF53, MONO_STAR>(a, s);
+        if (scheme == SWELDENS) return inv<CDF53, SWELDENS>(a, s);
+        if (scheme == IWAHASHI) return inv<CDF53, IWAHASHI>(a, s);
+    } else if (wavelet == CDF97) {
+        if (scheme == MONO_STAR) return inv<CDF97, MONO_STAR>(a, s);
+        if (scheme == SWELDENS) return inv<CDF97, SWELDENS>(a, s);
+        if (scheme == IWAHASHI) return inv<CDF97, IWAHASHI>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace dwt2

@@ -1,0 +1,190 @@
+"""Python binding of libdwt2 (the C ABI in include/dwt2.h).
+
+The functions named like the C entry points (``dwt2_forward`` ...) only
+marshal arguments.  ``forward`` / ``inverse`` are conveniences on top of them
+that allocate the output and workspace with torch on the input's device and
+enqueue on torch's current stream.  Every transform step runs in the HIP
+kernels of libdwt2.so; there is no CPU fallback: importing this module
+without a built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdwt2.so")
+
+OK, E_ARG, E_SIZE, E_UNSUPPORTED, E_WORKSPACE, E_ALIAS, E_HIP = 0, -1, -2, -3, -4, -5, -6
+CDF53, CDF97 = 0, 1
+EXT_WHOLE_SYMMETRIC = 0
+NORM_UNIT_DC, NORM_PAPER = 0, 1
+SCHEME_AUTO, SCHEME_MONOLITHIC_STAR, SCHEME_SWELDENS, SCHEME_IWAHASHI, SCHEME_ROWCOL = 0, 1, 2, 3, 4
+
+WAVELETS = {"cdf53": CDF53, "cdf97": CDF97, CDF53: CDF53, CDF97: CDF97}
+NORMS = {"unit_dc": NORM_UNIT_DC, "paper": NORM_PAPER, NORM_UNIT_DC: NORM_UNIT_DC,
+         NORM_PAPER: NORM_PAPER}
+SCHEMES = {"auto": SCHEME_AUTO, "monolithic*": SCHEME_MONOLITHIC_STAR,
+           "sweldens": SCHEME_SWELDENS, "iwahashi": SCHEME_IWAHASHI, "rowcol": SCHEME_ROWCOL}
+SCHEMES.update({v: v for v in list(SCHEMES.values())})
+
+EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_string",
+           "dwt2_last_hip_error", "dwt2_version"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_int), ("scheme", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
+
+
+class Dwt2Error(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = f"{what}: {dwt2_status_string(status)} (status {status})"
+        if status == E_HIP:
+            msg += f", hipError {dwt2_last_hip_error()}"
+        super().__init__(msg)
+        self.status = status
+
+
+def _load() -> ctypes.CDLL:
+    # One HIP runtime per process.  torch bundles its own libamdhip64 with the
+    # same soname (libamdhip64.so.7) as the system one libdwt2.so links to.  If
+    # torch is loaded first, libdwt2.so binds to torch's copy; if libdwt2.so
+    # came first, torch's NEEDED entry (libamdhip64.so) would not match and a
+    # second runtime would be loaded, and the two fail each other's calls.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1605_00561_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i, pd = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_ssize_t
+    L.dwt2_forward.argtypes = [i, i, i, i, vp, pd, vp, pd, i, ctypes.POINTER(Options), vp, sz, vp]
+    L.dwt2_inverse.argtypes = L.dwt2_forward.argtypes
+    L.dwt2_forward.restype = L.dwt2_inverse.restype = i
+    L.dwt2_workspace_bytes.argtypes = [i, i, i, i, ctypes.POINTER(Options), ctypes.POINTER(sz)]
+    L.dwt2_workspace_bytes.restype = i
+    L.dwt2_status_string.argtypes = [i]
+    L.dwt2_status_string.restype = ctypes.c_char_p
+    L.dwt2_last_hip_error.argtypes = []
+    L.dwt2_last_hip_error.restype = i
+    L.dwt2_version.argtypes = []
+    L.dwt2_version.restype = i
+    return L
+
+
+_lib = _load()
+
+
+def library() -> ctypes.CDLL:
+    return _lib
+
+
+def make_options(norm="unit_dc", scheme="auto") -> Options:
+    o = Options()
+    o.norm = NORMS[norm]
+    o.scheme = SCHEMES[scheme]
+    return o
+
+
+# --- C-ABI mirrors ------------------------------------------------------------
+def dwt2_version() -> int:
+    return _lib.dwt2_version()
+
+
+def dwt2_status_string(status: int) -> str:
+    return _lib.dwt2_status_string(int(status)).decode()
+
+
+def dwt2_last_hip_error() -> int:
+    return _lib.dwt2_last_hip_error()
+
+
+def dwt2_workspace_bytes(wavelet, levels, width, height, opt: Options | None = None):
+    """(status, bytes)."""
+    n = ctypes.c_size_t(0)
+    st = _lib.dwt2_workspace_bytes(WAVELETS[wavelet], levels, width, height,
+                                   ctypes.byref(opt) if opt is not None else None, ctypes.byref(n))
+    return st, n.value
+
+
+def dwt2_forward(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext,
+                 opt: Options | None, workspace, workspace_bytes, stream) -> int:
+    return _lib.dwt2_forward(WAVELETS[wavelet], levels, width, height, src, src_pitch, dst,
+                             dst_pitch, ext, ctypes.byref(opt) if opt is not None else None,
+                             workspace, workspace_bytes, stream)
+
+
+def dwt2_inverse(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext,
+                 opt: Options | None, workspace, workspace_bytes, stream) -> int:
+    return _lib.dwt2_inverse(WAVELETS[wavelet], levels, width, height, src, src_pitch, dst,
+                             dst_pitch, ext, ctypes.byref(opt) if opt is not None else None,
+                             workspace, workspace_bytes, stream)
+
+
+# --- torch conveniences -------------------------------------------------------
+def _check_image(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dim() != 2 or t.dtype != torch.float32:
+        raise TypeError("expected a 2-D float32 torch tensor")
+    if not t.is_cuda:
+        raise TypeError("expected a device tensor (libdwt2 runs on the GPU only)")
+    if t.stride(1) != 1:
+        raise ValueError("rows must be contiguous (stride(1) == 1)")
+
+
+def _workspace(wavelet, levels, w, h, opt, device, workspace):
+    import torch
+    st, nbytes = dwt2_workspace_bytes(wavelet, levels, w, h, opt)
+    if st != OK:
+        raise Dwt2Error(st, "dwt2_workspace_bytes")
+    if nbytes == 0:
+        return None, 0
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return workspace, workspace.numel() * workspace.element_size()
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
+            workspace=None, stream=None):
+    """Forward DWT of a (H, W) float32 device tensor; returns the Mallat layout."""
+    import torch
+    _check_image(img)
+    h, w = img.shape
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=img.device)
+    _check_image(out)
+    opt = make_options(norm, scheme)
+    ws, nws = _workspace(wavelet, levels, w, h, opt, img.device, workspace)
+    st = dwt2_forward(wavelet, levels, w, h, img.data_ptr(), img.stride(0), out.data_ptr(),
+                      out.stride(0), EXT_WHOLE_SYMMETRIC, opt,
+                      ws.data_ptr() if ws is not None else None, nws, _stream_handle(stream))
+    if st != OK:
+        raise Dwt2Error(st, "dwt2_forward")
+    return out
+
+
+def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
+            workspace=None, stream=None):
+    """Inverse DWT of a (H, W) Mallat-layout float32 device tensor; returns the image."""
+    import torch
+    _check_image(coef)
+    h, w = coef.shape
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=coef.device)
+    _check_image(out)
+    opt = make_options(norm, scheme)
+    ws, nws = _workspace(wavelet, levels, w, h, opt, coef.device, workspace)
+    st = dwt2_inverse(wavelet, levels, w, h, coef.data_ptr(), coef.stride(0), out.data_ptr(),
+                      out.stride(0), EXT_WHOLE_SYMMETRIC, opt,
+                      ws.data_ptr() if ws is not None else None, nws, _stream_handle(stream))
+    if st != OK:
+        raise Dwt2Error(st, "dwt2_inverse")
+    return out

@@ -1,0 +1,150 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/dwt2.h declares, and rejects bad arguments on the host before any
+launch.  No call here is valid, so nothing is ever enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1605_00561_amd import dwt2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dwt2.h")
+FAKE = 0x7F0000000000  # never dereferenced: every call below fails validation
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dwt2_\w+)\s*\(", text)))
+
+
+def header_define(name):
+    m = re.search(rf"#define\s+{name}\s+\(?(-?\d+)\)?", open(HEADER).read())
+    return int(m.group(1))
+
+
+def test_exports_every_declared_function():
+    names = header_functions()
+    assert set(names) == set(dwt2.EXPORTS)
+    lib = ctypes.CDLL(dwt2.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_status_codes_match_header():
+    assert dwt2.dwt2_version() == header_define("DWT2_VERSION")
+    for name, val in [("DWT2_OK", dwt2.OK), ("DWT2_E_ARG", dwt2.E_ARG),
+                      ("DWT2_E_SIZE", dwt2.E_SIZE), ("DWT2_E_UNSUPPORTED", dwt2.E_UNSUPPORTED),
+                      ("DWT2_E_WORKSPACE", dwt2.E_WORKSPACE), ("DWT2_E_ALIAS", dwt2.E_ALIAS),
+                      ("DWT2_E_HIP", dwt2.E_HIP)]:
+        assert header_define(name) == val
+        assert dwt2.dwt2_status_string(val) != "unknown status"
+    assert dwt2.dwt2_status_string(12345) == "unknown status"
+    assert dwt2.dwt2_last_hip_error() == 0
+
+
+def _ws(wav, lev, w, h, scheme="auto"):
+    st, n = dwt2.dwt2_workspace_bytes(wav, lev, w, h, dwt2.make_options(scheme=scheme))
+    assert st == dwt2.OK
+    return n
+
+
+def _al(n):
+    return (n + 255) // 256 * 256
+
+
+def test_workspace_bytes():
+    assert _ws("cdf53", 1, 512, 512) == 0
+    assert _ws("cdf97", 1, 8192, 8192) == 0
+    assert _ws("cdf97", 2, 100, 60) == _al(4 * 50 * 30)
+    assert _ws("cdf53", 5, 101, 61) == _al(4 * 51 * 31) + _al(4 * 26 * 16)
+    assert _ws("cdf53", 1, 100, 60, "rowcol") == _al(4 * 100 * 60)
+    assert _ws("cdf97", 3, 100, 60, "rowcol") == _al(4 * 50 * 30) + _al(4 * 25 * 15) + _al(4 * 6000)
+    st, _ = dwt2.dwt2_workspace_bytes("cdf53", 1, 1, 8, None)
+    assert st == dwt2.E_SIZE
+    n = ctypes.c_size_t()
+    assert dwt2.library().dwt2_workspace_bytes(0, 1, 8, 8, None, None) == dwt2.E_ARG
+    assert dwt2.library().dwt2_workspace_bytes(5, 1, 8, 8, None, ctypes.byref(n)) == \
+        dwt2.E_UNSUPPORTED
+
+
+def _fwd(**kw):
+    a = dict(wavelet=0, levels=1, width=16, height=16, src=FAKE, src_pitch=16,
+             dst=FAKE + (1 << 24), dst_pitch=16, ext=0, opt=None, workspace=None,
+             workspace_bytes=0, stream=None)
+    a.update(kw)
+    lib = dwt2.library()
+    res = []
+    for f in (lib.dwt2_forward, lib.dwt2_inverse):
+        res.append(f(a["wavelet"], a["levels"], a["width"], a["height"], a["src"], a["src_pitch"],
+                     a["dst"], a["dst_pitch"], a["ext"],
+                     ctypes.byref(a["opt"]) if a["opt"] is not None else None,
+                     a["workspace"], a["workspace_bytes"], a["stream"]))
+    assert res[0] == res[1]
+    return res[0]
+
+
+def test_argument_errors():
+    assert _fwd(src=None) == dwt2.E_ARG
+    assert _fwd(dst=None) == dwt2.E_ARG
+    assert _fwd(width=0) == dwt2.E_ARG
+    assert _fwd(height=-3) == dwt2.E_ARG
+    assert _fwd(levels=0) == dwt2.E_ARG
+    assert _fwd(src_pitch=15) == dwt2.E_ARG
+    assert _fwd(dst_pitch=8) == dwt2.E_ARG
+    assert _fwd(src=FAKE + 2) == dwt2.E_ARG  # not 4-byte aligned
+    o = dwt2.make_options()
+    o.reserved[3] = 1
+    assert _fwd(opt=o) == dwt2.E_ARG
+
+
+def test_size_errors():
+    assert _fwd(width=1, src_pitch=1, dst_pitch=1) == dwt2.E_SIZE
+    assert _fwd(height=1) == dwt2.E_SIZE
+    assert _fwd(levels=5) == dwt2.E_SIZE        # 16 -> 8 -> 4 -> 2 -> 1
+    assert _fwd(levels=40) == dwt2.E_SIZE
+
+
+def test_unsupported():
+    assert _fwd(wavelet=2) == dwt2.E_UNSUPPORTED
+    assert _fwd(ext=1) == dwt2.E_UNSUPPORTED
+    o = dwt2.make_options()
+    o.norm = 2
+    assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
+    o = dwt2.make_options()
+    o.scheme = 9
+    assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
+
+
+def test_workspace_and_alias_errors():
+    assert _fwd(levels=2) == dwt2.E_WORKSPACE           # needs a workspace
+    assert _fwd(levels=2, workspace=FAKE + (2 << 24), workspace_bytes=16) == dwt2.E_WORKSPACE
+    assert _fwd(levels=2, workspace=FAKE + (2 << 24) + 4, workspace_bytes=4096) == dwt2.E_ARG
+    assert _fwd(dst=FAKE) == dwt2.E_ALIAS                # dst == src
+    assert _fwd(dst=FAKE + 4 * 16 * 15) == dwt2.E_ALIAS  # last row of src overlaps dst
+    assert _fwd(levels=2, workspace=FAKE + (1 << 24), workspace_bytes=4096) == dwt2.E_ALIAS
+
+
+def test_torch_wrappers_reject_host_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        dwt2.forward(torch.zeros(8, 8))
+    with pytest.raises(TypeError):
+        dwt2.inverse(torch.zeros(8, 8, dtype=torch.float64))
+
+
+def test_single_hip_runtime_when_binding_is_imported_first():
+    """Importing the binding before torch must not leave two HIP runtimes mapped
+    (torch's bundled libamdhip64 and the system one): with two, every launch of
+    one fails in the other's context."""
+    import subprocess
+    import sys
+    code = ("import paper_1605_00561_amd.dwt2, torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

@@ -1,0 +1,212 @@
+"""GPU parity: libdwt2 (HIP, through the C ABI) against the FP64 oracle.
+
+Bar (FP32 kernels vs FP64 oracle, inputs in [0, 255]):
+  * CDF 5/3 on integer input, one level (two with UNIT_DC): bit-exact -- every
+    intermediate is a small dyadic rational, exactly representable in FP32;
+  * otherwise max |gpu - oracle| <= 1e-3 and ||gpu - oracle||_2 / ||oracle||_2
+    <= 1e-6, with the oracle run on the same FP32 input values.
+Inverse parity compares the GPU inverse of a set of FP32 coefficients with the
+oracle's inverse of the same coefficients.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1605_00561_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1605_00561_amd import dwt2  # noqa: E402
+
+SCHEMES = ["monolithic*", "sweldens", "iwahashi", "rowcol"]
+WAVS = ["cdf53", "cdf97"]
+MAX_ABS, REL_L2 = 1e-3, 1e-6
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def to_dev(a, pitch=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    h, w = a.shape
+    if pitch is None or pitch == w:
+        return torch.from_numpy(a).to(dev())
+    buf = torch.full((h, pitch), float("nan"), dtype=torch.float32, device=dev())
+    buf[:, :w] = torch.from_numpy(a).to(dev())
+    return buf[:, :w]
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def empty_dev(h, w, pitch=None):
+    if pitch is None:
+        return torch.full((h, w), float("nan"), dtype=torch.float32, device=dev())
+    return torch.full((h, pitch), float("nan"), dtype=torch.float32, device=dev())[:, :w]
+
+
+def check(got, ref, exact, what):
+    assert np.all(np.isfinite(got)), f"{what}: non-finite output"
+    d = got - ref
+    mx = float(np.abs(d).max())
+    rel = float(np.linalg.norm(d) / max(np.linalg.norm(ref), 1e-300))
+    if exact:
+        assert mx == 0.0, f"{what}: not bit-exact, max |d| = {mx:.3e}"
+    else:
+        assert mx <= MAX_ABS and rel <= REL_L2, f"{what}: max |d| = {mx:.3e}, rel-L2 = {rel:.3e}"
+    return mx, rel
+
+
+def max_levels(w, h, cap):
+    n = 0
+    while n < cap and w >= 2 and h >= 2:
+        n += 1
+        w, h = (w + 1) // 2, (h + 1) // 2
+    return n
+
+
+def exact_expected(wav, lev, norm):
+    return wav == "cdf53" and (lev == 1 or (lev == 2 and norm == "unit_dc"))
+
+
+def run_case(x, wav, lev, norm, scheme, pitch=None):
+    h, w = x.shape
+    xd = to_dev(x, pitch)
+    y = dwt2.forward(xd, wav, lev, norm, scheme, out=empty_dev(h, w, pitch))
+    ref = oracle.forward(x.astype(np.float64), wav, lev, norm)
+    got = to_host(y)
+    check(got, ref, exact_expected(wav, lev, norm), f"fwd {scheme} {wav} {norm} {w}x{h} L{lev}")
+    # inverse of the GPU's own FP32 coefficients vs the oracle's inverse of them
+    z = dwt2.inverse(y, wav, lev, norm, scheme, out=empty_dev(h, w, pitch))
+    ref_inv = oracle.inverse(got, wav, lev, norm)
+    check(to_host(z), ref_inv, exact_expected(wav, lev, norm),
+          f"inv {scheme} {wav} {norm} {w}x{h} L{lev}")
+    return got
+
+
+SMALL_SHAPES = [(2, 2), (3, 2), (2, 3), (5, 7), (9, 4), (16, 16), (37, 22), (65, 33),
+                (127, 131), (300, 500), (520, 131), (1030, 770)]
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("wav", WAVS)
+def test_single_level_small(scheme, wav):
+    rng = np.random.default_rng(100)
+    for (w, h) in SMALL_SHAPES:
+        x = rng.integers(0, 256, size=(h, w)).astype(np.float32)
+        for norm in ("unit_dc", "paper"):
+            run_case(x, wav, 1, norm, scheme)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("wav", WAVS)
+def test_multi_level(scheme, wav):
+    rng = np.random.default_rng(101)
+    for (w, h) in [(258, 130), (301, 203), (1000, 999), (64, 3000)]:
+        x = rng.integers(0, 256, size=(h, w)).astype(np.float32)
+        for lev in sorted({2, 3, max_levels(w, h, 7)}):
+            run_case(x, wav, lev, "unit_dc", scheme)
+        run_case(x, wav, 3, "paper", scheme)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_pitched_buffers(scheme):
+    rng = np.random.default_rng(102)
+    x = rng.integers(0, 256, size=(97, 203)).astype(np.float32)
+    for wav in WAVS:
+        run_case(x, wav, 3, "unit_dc", scheme, pitch=211)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_deepest_levels_to_2x2(scheme):
+    """Levels down to a 2x2 last input; tiny inputs reflect the halo several times."""
+    rng = np.random.default_rng(103)
+    for (w, h) in [(64, 64), (33, 17), (2, 2), (3, 3), (6, 5)]:
+        x = rng.integers(0, 256, size=(h, w)).astype(np.float32)
+        for wav in WAVS:
+            run_case(x, wav, max_levels(w, h, 30), "unit_dc", scheme)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_schemes_agree_bitwise_on_5_3(scheme):
+    """5/3 on integer input is exact, so every scheme gives identical bits."""
+    x = wl.uniform_u8(777, 555, seed=104)
+    ref = to_host(dwt2.forward(to_dev(x), "cdf53", 1, "paper", "monolithic*"))
+    got = to_host(dwt2.forward(to_dev(x), "cdf53", 1, "paper", scheme))
+    assert np.array_equal(ref, got)
+
+
+@pytest.mark.parametrize("wav", WAVS)
+def test_normalisation_relation_bitwise(wav):
+    """PAPER = UNIT_DC x 2^(k-1) x {2, 1, 1, 1/2} per subband, bit for bit."""
+    x = wl.uniform_u8(301, 187, seed=105)
+    lev = 4
+    u = to_host(dwt2.forward(to_dev(x), wav, lev, "unit_dc"))
+    p = to_host(dwt2.forward(to_dev(x), wav, lev, "paper"))
+    ratio = np.ones_like(u)
+    wk, hk = 301, 187
+    for k in range(1, lev + 1):
+        wl_, hl_ = (wk + 1) // 2, (hk + 1) // 2
+        f = 2.0 ** (k - 1)
+        ratio[:hl_, wl_:wk] = f
+        ratio[hl_:hk, :wl_] = f
+        ratio[hl_:hk, wl_:wk] = f / 2
+        ratio[:hl_, :wl_] = 2 * f
+        wk, hk = wl_, hl_
+    assert np.array_equal(p, u * ratio)
+
+
+def test_constant_and_ramp_images():
+    h, w = 90, 131
+    c = np.full((h, w), 77.0, dtype=np.float32)
+    for wav in WAVS:
+        y = to_host(dwt2.forward(to_dev(c), wav, 3))
+        ref = oracle.forward(c.astype(np.float64), wav, 3)
+        check(y, ref, wav == "cdf53", f"constant {wav}")
+    yy, xx = np.mgrid[0:h, 0:w]
+    ramp = (3 + 1.5 * xx + 0.5 * yy).astype(np.float32)
+    y = to_host(dwt2.forward(to_dev(ramp), "cdf53", 1))
+    hl, wl_ = (h + 1) // 2, (w + 1) // 2
+    assert np.all(y[hl:, wl_:] == 0)          # HH of a ramp is zero (5/3)
+    assert np.all(y[:hl, wl_:] == 0)          # W odd: HL zero everywhere
+
+
+# --- full workload sizes ---------------------------------------------------------
+def test_workload_cdf53_512():
+    x = wl.workload_image("cdf53_512_l1")
+    for scheme in SCHEMES:
+        run_case(x, "cdf53", 1, "unit_dc", scheme)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_workload_cdf97_8192(scheme):
+    x = wl.workload_image("cdf97_8192_l1")
+    ref = oracle.forward(x.astype(np.float64), "cdf97", 1)
+    xd = to_dev(x)
+    y = dwt2.forward(xd, "cdf97", 1, "unit_dc", scheme)
+    got = to_host(y)
+    check(got, ref, False, f"fwd {scheme} cdf97 8192")
+    z = to_host(dwt2.inverse(y, "cdf97", 1, "unit_dc", scheme))
+    check(z, oracle.inverse(got, "cdf97", 1), False, f"inv {scheme} cdf97 8192")
+    check(z, x.astype(np.float64), False, f"round trip {scheme} cdf97 8192")
+
+
+@pytest.mark.parametrize("wav", WAVS)
+def test_workload_16384_five_levels(wav):
+    x = wl.workload_image(f"{wav}_16384_l5")
+    ref = oracle.forward(x.astype(np.float64), wav, 5)
+    xd = to_dev(x)
+    del x
+    y = dwt2.forward(xd, wav, 5)
+    got = to_host(y)
+    check(got, ref, False, f"fwd {wav} 16384 L5")
+    del ref
+    z = dwt2.inverse(y, wav, 5)
+    rt = to_host(z)
+    check(rt, to_host(xd), False, f"round trip {wav} 16384 L5")
