@@ -44,24 +44,26 @@ def parse():
                     help="approximate CPU time budget for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-schemes", action="store_true")
+    ap.add_argument("--no-copy", action="store_true",
+                    help="skip the device-to-device copy (the bandwidth and counter reference)")
     return ap.parse_args()
 
 
-def traffic_from_profiles(kernel_tag: str):
-    """HBM bytes per launch of the dominant kernel from committed PMC counters,
-    or None when absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_hbm_counters.json")
+def traffic_from_profiles(tag: str):
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when it is
+    absent or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{tag}_hbm_counters.json")
     if not os.path.exists(path):
         return None
     try:
         import hashlib
         rec = json.load(open(path))
-        src = os.path.join(ROOT, rec["source"])
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if digest != rec["source_sha256"]:
+        blob = b"".join(open(os.path.join(ROOT, s), "rb").read() for s in rec["sources"])
+        if hashlib.sha256(blob).hexdigest() != rec["sources_sha256"]:
             return None
-        return float(rec["bytes_per_launch"])
-    except Exception:
+        return int(round(rec["bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
         return None
 
 
@@ -116,7 +118,7 @@ def main():
 
     fwd_mean = statistics.fmean(fwd_ms)
     achieved = BYTES_PER_PX * npx / (fwd_mean * 1e-3) / 1e9
-    traffic = traffic_from_profiles("tile_forward_cdf97_mono")
+    traffic = traffic_from_profiles("tile_forward_cdf97_mono_8192")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
@@ -144,6 +146,7 @@ def main():
 
     if not args.no_schemes:
         out["schemes"] = scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, args.scheme_reps)
+    if not args.no_copy:
         out["copy_GBs"] = copy_bandwidth(torch, dev)
 
     if not args.no_cpu_baseline:

@@ -218,6 +218,8 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
         a.W = W;
         a.H = H;
         a.s = s;
+        a.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
+        a.quantum = c.cfg.norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
         if (k == levels - 1) {
             a.ll = dst;
             a.ll_pitch = dst_pitch;
@@ -263,6 +265,8 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
         a.W = W;
         a.H = H;
         a.inv_s = r;
+        a.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
+        a.quantum = c.cfg.norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
         if (k == 0) {
             a.out = dst;
             a.out_pitch = dst_pitch;

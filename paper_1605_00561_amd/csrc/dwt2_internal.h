@@ -61,6 +61,12 @@ __host__ __device__ __forceinline__ int ws_mirror(int j, int n)
 
 // One forward level: `in` (W x H) -> LL into `ll`, HL/LH/HH into the Mallat
 // positions of `det` (HL at column ceil(W/2), LH at row ceil(H/2)).
+//
+// Centering (tile kernels): a tile may subtract any constant c from all the
+// samples it reads and add the transform of the constant image back, which is
+// c * ll_gain in LL and zero elsewhere; by linearity the result is unchanged.
+// c is rounded to a multiple of `quantum` (the level input's power-of-two
+// scale), so integer data stay integer and results scale exactly with it.
 struct FwdArgs {
     const float *in;
     ptrdiff_t in_pitch;
@@ -70,6 +76,8 @@ struct FwdArgs {
     ptrdiff_t det_pitch;
     int W, H;
     Scale s;
+    float ll_gain;  // LL of a constant image c is c * ll_gain (1 UNIT_DC, 2 PAPER)
+    float quantum;  // c is a multiple of this power of two
 };
 
 // One inverse level: LL from `ll`, HL/LH/HH from `det` -> `out` (W x H).
@@ -82,6 +90,8 @@ struct InvArgs {
     ptrdiff_t out_pitch;
     int W, H;
     Scale inv_s;  // reciprocal scales
+    float ll_gain;
+    float quantum;
 };
 
 // Launch `kern` and return the status of this launch only (hipLaunchKernel

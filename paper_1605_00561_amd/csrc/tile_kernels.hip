@@ -26,6 +26,15 @@
 // mirroring.  After pair k only quadruples at least k+1 from the tile edge
 // are valid; the interior (TX - 2K) x (TY - 2K) quadruples are stored.
 //
+// FP32 conditioning: every tile subtracts a constant c (the rounded mean of
+// its middle quadruple row) from all samples before lifting and adds
+// c * ll_gain to LL at the end -- exact by linearity, since every stored
+// quadruple depends only on samples inside the tile.  Flat regions then
+// transform near zero instead of through the large 9/7 intermediates
+// (1 + 2 alpha ~ -2.17 times the sample value), which cuts FP32 rounding.
+// All waves compute c from the same samples in the same order, so it is
+// bitwise identical across the work-group without a barrier.
+//
 // Work-groups are numbered so that each of the 8 XCDs (workgroup id mod 8)
 // receives a contiguous run of tiles in row-major order, so the halo rows
 // and columns shared by neighbouring tiles are re-read from the same L2.
@@ -60,6 +69,14 @@ __device__ __forceinline__ float &cell(float *lds, int pl, int r, int c)
 struct Quads {
     float v[NJ][4];
 };
+
+// Sum over the 64 lanes by an xor butterfly: every lane ends with the same bits.
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
 
 template <int C>
 __device__ __forceinline__ void publish(float *lds, int pl, const Quads &q, int lane, int wv)
@@ -387,6 +404,19 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_forward(FwdArgs a, int ntx, i
         q.v[j][LH] = r1[x0];
         q.v[j][HH] = r1[x1];
     }
+    // Tile constant: mean of the middle quadruple row (256 samples).
+    float c;
+    {
+        const int qm = tr * IY - HQ + TY / 2;
+        const float *m0 = a.in + (ptrdiff_t)ws_mirror(2 * qm, H) * a.in_pitch;
+        const float *m1 = a.in + (ptrdiff_t)ws_mirror(2 * qm + 1, H) * a.in_pitch;
+        const float sum = wave_sum((m0[x0] + m0[x1]) + (m1[x0] + m1[x1]));
+        c = rintf(sum * (1.0f / (4 * TX)) / a.quantum) * a.quantum;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; j++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) q.v[j][e] -= c;
 
     transform_tile<WAV, SCH, false>(lds, q, lane, wv);
 
@@ -396,7 +426,7 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_forward(FwdArgs a, int ntx, i
         const int r = j * NWAVES + wv;
         const int qr = tr * IY - HQ + r;
         if (r < HQ || r >= TY - HQ || qr >= QH) continue;
-        a.ll[(ptrdiff_t)qr * a.ll_pitch + qc] = q.v[j][LL] * a.s.ll;
+        a.ll[(ptrdiff_t)qr * a.ll_pitch + qc] = fmaf(q.v[j][LL], a.s.ll, c * a.ll_gain);
         float *drow = a.det + (ptrdiff_t)qr * a.det_pitch;
         if (qc < WH) drow[QW + qc] = q.v[j][HL];
         if (qr < HH_) {
@@ -423,6 +453,17 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_inverse(InvArgs a, int ntx, i
     // Coefficient columns of the mirrored L and H samples (mirroring keeps parity).
     const int cl = ws_mirror(2 * qc, W) >> 1, ch = ws_mirror(2 * qc + 1, W) >> 1;
 
+    // Tile constant in the pixel domain from the LL coefficients of the middle
+    // quadruple row: LL of a constant image c is c * ll_gain.
+    float c;
+    {
+        const int qm = tr * IY - HQ + TY / 2;
+        const int rm = ws_mirror(2 * qm, H) >> 1;
+        const float sum = wave_sum(a.ll[(ptrdiff_t)rm * a.ll_pitch + cl]);
+        c = rintf(sum * (1.0f / TX) / (a.ll_gain * a.quantum)) * a.quantum;
+    }
+    const float cll = c * a.ll_gain;
+
     Quads q;
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
@@ -430,7 +471,7 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_inverse(InvArgs a, int ntx, i
         const int rl = ws_mirror(2 * qr, H) >> 1, rh = ws_mirror(2 * qr + 1, H) >> 1;
         const float *lrow = a.det + (ptrdiff_t)rl * a.det_pitch;
         const float *hrow = a.det + (ptrdiff_t)(QH + rh) * a.det_pitch;
-        q.v[j][LL] = a.ll[(ptrdiff_t)rl * a.ll_pitch + cl] * a.inv_s.ll;
+        q.v[j][LL] = (a.ll[(ptrdiff_t)rl * a.ll_pitch + cl] - cll) * a.inv_s.ll;
         q.v[j][HL] = lrow[QW + ch];
         q.v[j][LH] = hrow[cl];
         q.v[j][HH] = hrow[QW + ch] * a.inv_s.hh;
@@ -447,12 +488,12 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_inverse(InvArgs a, int ntx, i
         if (r < HQ || r >= TY - HQ || qr >= QH) continue;
         const int py = 2 * qr;
         float *o0 = a.out + (ptrdiff_t)py * a.out_pitch;
-        o0[px] = q.v[j][LL];
-        if (px + 1 < W) o0[px + 1] = q.v[j][HL];
+        o0[px] = q.v[j][LL] + c;
+        if (px + 1 < W) o0[px + 1] = q.v[j][HL] + c;
         if (py + 1 < H) {
             float *o1 = o0 + a.out_pitch;
-            o1[px] = q.v[j][LH];
-            if (px + 1 < W) o1[px + 1] = q.v[j][HH];
+            o1[px] = q.v[j][LH] + c;
+            if (px + 1 < W) o1[px + 1] = q.v[j][HH] + c;
         }
     }
 }

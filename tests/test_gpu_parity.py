@@ -2,7 +2,10 @@
 
 Bar (FP32 kernels vs FP64 oracle, inputs in [0, 255]):
   * CDF 5/3 on integer input, one level (two with UNIT_DC): bit-exact -- every
-    intermediate is a small dyadic rational, exactly representable in FP32;
+    intermediate is a small dyadic rational, exactly representable in FP32.  The
+    exact value is the oracle's snapped to the 2^-16 grid: the FP64 oracle may sit
+    an FP64 rounding away from it, since with PAPER scaling it multiplies by
+    sqrt(2) twice;
   * otherwise max |gpu - oracle| <= 1e-3 and ||gpu - oracle||_2 / ||oracle||_2
     <= 1e-6, with the oracle run on the same FP32 input values.
 Inverse parity compares the GPU inverse of a set of FP32 coefficients with the
@@ -57,7 +60,10 @@ def check(got, ref, exact, what):
     mx = float(np.abs(d).max())
     rel = float(np.linalg.norm(d) / max(np.linalg.norm(ref), 1e-300))
     if exact:
-        assert mx == 0.0, f"{what}: not bit-exact, max |d| = {mx:.3e}"
+        snapped = np.round(ref * 65536.0) / 65536.0
+        assert np.abs(snapped - ref).max() < 1e-9, f"{what}: oracle value off the dyadic grid"
+        assert np.array_equal(got, snapped), \
+            f"{what}: not bit-exact, max |d| = {float(np.abs(got - snapped).max()):.3e}"
     else:
         assert mx <= MAX_ABS and rel <= REL_L2, f"{what}: max |d| = {mx:.3e}, rel-L2 = {rel:.3e}"
     return mx, rel
@@ -194,7 +200,9 @@ def test_workload_cdf97_8192(scheme):
     check(got, ref, False, f"fwd {scheme} cdf97 8192")
     z = to_host(dwt2.inverse(y, "cdf97", 1, "unit_dc", scheme))
     check(z, oracle.inverse(got, "cdf97", 1), False, f"inv {scheme} cdf97 8192")
-    check(z, x.astype(np.float64), False, f"round trip {scheme} cdf97 8192")
+    d = z - x.astype(np.float64)
+    assert np.abs(d).max() <= 2 * MAX_ABS                       # round trip: two transforms
+    assert np.linalg.norm(d) / np.linalg.norm(x.astype(np.float64)) <= REL_L2
 
 
 @pytest.mark.parametrize("wav", WAVS)
@@ -202,11 +210,14 @@ def test_workload_16384_five_levels(wav):
     x = wl.workload_image(f"{wav}_16384_l5")
     ref = oracle.forward(x.astype(np.float64), wav, 5)
     xd = to_dev(x)
-    del x
     y = dwt2.forward(xd, wav, 5)
     got = to_host(y)
     check(got, ref, False, f"fwd {wav} 16384 L5")
     del ref
-    z = dwt2.inverse(y, wav, 5)
-    rt = to_host(z)
-    check(rt, to_host(xd), False, f"round trip {wav} 16384 L5")
+    z = to_host(dwt2.inverse(y, wav, 5))
+    check(z, oracle.inverse(got, wav, 5), False, f"inv {wav} 16384 L5")
+    # GPU forward then GPU inverse composes two FP32 transforms, each within
+    # the bar above, so the round trip is held to twice the max-abs bound.
+    d = z - x.astype(np.float64)
+    assert np.abs(d).max() <= 2 * MAX_ABS
+    assert np.linalg.norm(d) / np.linalg.norm(x.astype(np.float64)) <= REL_L2
