@@ -11,8 +11,10 @@ line:
   roofline     the fused forward kernel against the HBM roofline: algorithmic
                bytes (4 B read + 4 B written per pixel) / its mean duration,
                timed with HIP events on the launch stream
-  schemes      per-scheme forward / inverse Gpixel/s and % of 8 TB/s
-               (fused Monolithic*, separable Sweldens and row-column, Iwahashi)
+  schemes      per-scheme forward / inverse Gpixel/s and % of 8 TB/s: the fused
+               register-blocked Monolithic*, and in the LDS tile harness
+               Monolithic* (2 barriers per pair), separable Sweldens (4) and
+               Iwahashi (3), plus the row-column separable two-pass kernels
   cpu_baseline the FP64 CPU oracle on the host cores, forward + inverse of the
                same image
 """
@@ -118,11 +120,11 @@ def main():
 
     fwd_mean = statistics.fmean(fwd_ms)
     achieved = BYTES_PER_PX * npx / (fwd_mean * 1e-3) / 1e9
-    traffic = traffic_from_profiles("tile_forward_cdf97_mono_8192")
+    traffic = traffic_from_profiles("fused_forward_cdf97_8192")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "k_tile_forward<CDF97, MONO_STAR>",
+                "kernel": "k_fused_forward<CDF97>",
                 "algorithmic_bytes_per_launch": int(BYTES_PER_PX * npx),
                 "mean_launch_us": round(fwd_mean * 1e3, 2),
                 "inverse_mean_launch_us": round(statistics.fmean(inv_ms) * 1e3, 2)}
@@ -158,7 +160,10 @@ def main():
 def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
     stream = torch.cuda.current_stream()
     table = {}
-    for scheme in ("monolithic*", "sweldens", "iwahashi", "rowcol"):
+    for name in ("monolithic*", "monolithic*:fp64", "monolithic*-tile", "sweldens", "iwahashi",
+                 "rowcol"):
+        scheme, _, arith = name.partition(":")
+        arith = arith or "auto"
         ws = None
         st, nbytes = dwt2.dwt2_workspace_bytes(wav, lev, xs[0].shape[1], xs[0].shape[0],
                                                dwt2.make_options(scheme=scheme))
@@ -169,13 +174,15 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
             f = dwt2.forward if direction == "forward" else dwt2.inverse
             src, dst = (xs, ys) if direction == "forward" else (ys, zs)
             for i in range(2):
-                f(src[i % NSETS], wav, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws)
+                f(src[i % NSETS], wav, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws,
+                  arithmetic=arith)
             ms = []
             for i in range(reps):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                f(src[i % NSETS], wav, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws)
+                f(src[i % NSETS], wav, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws,
+                  arithmetic=arith)
                 e1.record(stream)
                 ms.append((e0, e1))
             torch.cuda.synchronize()
@@ -183,7 +190,7 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
             gbs = BYTES_PER_PX * npx / (t * 1e-3) / 1e9
             res[direction] = {"us": round(t * 1e3, 2), "Gpixel_s": round(npx / (t * 1e-3) / 1e9, 1),
                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-        table[scheme] = res
+        table[name] = res
     return table
 
 

@@ -55,7 +55,7 @@ extern "C" {
 #define DWT2_OK 0
 #define DWT2_E_ARG (-1)         /* null pointer, non-positive size, pitch < width, bad levels */
 #define DWT2_E_SIZE (-2)        /* some level's input is smaller than 2 x 2 */
-#define DWT2_E_UNSUPPORTED (-3) /* unknown wavelet, extension, normalisation or scheme */
+#define DWT2_E_UNSUPPORTED (-3) /* unknown wavelet, extension, normalisation, scheme or arithmetic */
 #define DWT2_E_WORKSPACE (-4)   /* workspace missing or smaller than dwt2_workspace_bytes() */
 #define DWT2_E_ALIAS (-5)       /* src and dst (or workspace) overlap */
 #define DWT2_E_HIP (-6)         /* a HIP launch failed; see dwt2_last_hip_error() */
@@ -83,27 +83,42 @@ typedef enum dwt2_norm { DWT2_NORM_UNIT_DC = 0, DWT2_NORM_PAPER = 1 } dwt2_norm;
 /*
  * Scheme of the per-level kernel.  All give the same coefficients up to FP32
  * rounding (bit-identical for integer input with CDF 5/3).
- *   MONOLITHIC_STAR  fused tile kernel, 2 barriers per lifting pair (Sec. 4).
- *   SWELDENS         separable steps T^H_P | T^V_P | S^H_U | S^V_U in the same
- *                    tile harness, 4 barriers per pair (Sec. 2).
- *   IWAHASHI         earlier non-separable T^I_P | R^I_{P,U} | S^I_U in the
- *                    same harness, 3 barriers per pair (Sec. 2).
- *   ROWCOL           row pass then column pass through device memory.
- *   AUTO             the fastest implemented scheme (MONOLITHIC_STAR).
+ *   MONOLITHIC_STAR       the paper's Monolithic* steps (Sec. 4) in the fused
+ *                         kernel: a tile plus halo per work-group held in
+ *                         registers, horizontal neighbours by wavefront
+ *                         shifts, LDS only at the seams between wavefronts,
+ *                         2 barriers per lifting pair.  AUTO selects it.
+ *   MONOLITHIC_STAR_TILE  the same steps in the block-based tile harness (every
+ *                         neighbour exchanged through LDS, 2 barriers per pair).
+ *   SWELDENS              separable steps T^H_P | T^V_P | S^H_U | S^V_U in the
+ *                         tile harness, 4 barriers per pair (Sec. 2).
+ *   IWAHASHI              earlier non-separable T^I_P | R^I_{P,U} | S^I_U in the
+ *                         tile harness, 3 barriers per pair (Sec. 2).
+ *   ROWCOL                separable row pass then column pass through memory.
  */
 typedef enum dwt2_scheme {
     DWT2_SCHEME_AUTO = 0,
     DWT2_SCHEME_MONOLITHIC_STAR = 1,
     DWT2_SCHEME_SWELDENS = 2,
     DWT2_SCHEME_IWAHASHI = 3,
-    DWT2_SCHEME_ROWCOL = 4
+    DWT2_SCHEME_ROWCOL = 4,
+    DWT2_SCHEME_MONOLITHIC_STAR_TILE = 5
 } dwt2_scheme;
 
-/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO). */
+/*
+ * Arithmetic of the lifting steps.  Samples and coefficients are FP32 in
+ * memory in every case.  FP64 keeps the intermediate values of the fused
+ * MONOLITHIC_STAR kernel in double precision (other schemes: FP32 only,
+ * DWT2_E_UNSUPPORTED).  AUTO selects FP32.
+ */
+typedef enum dwt2_arith { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_ARITH_FP64 = 2 } dwt2_arith;
+
+/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO). */
 typedef struct dwt2_options {
-    int norm;   /* dwt2_norm */
-    int scheme; /* dwt2_scheme */
-    int reserved[6]; /* must be zero */
+    int norm;        /* dwt2_norm */
+    int scheme;      /* dwt2_scheme */
+    int arithmetic;  /* dwt2_arith */
+    int reserved[5]; /* must be zero */
 } dwt2_options;
 
 /*

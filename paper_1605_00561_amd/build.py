@@ -24,7 +24,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdwt2.so")
 ARCH = os.environ.get("DWT2_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["dwt2_api.cpp", "tile_kernels.hip", "rowcol_kernels.hip"]
+SOURCES = ["dwt2_api.cpp", "tile_kernels.hip", "fused_kernels.hip", "rowcol_kernels.hip"]
 HEADERS = ["dwt2_internal.h"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

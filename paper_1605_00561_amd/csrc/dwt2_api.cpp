@@ -21,7 +21,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Config {
-    int wavelet, norm, scheme;
+    int wavelet, norm, scheme, arithmetic;
 };
 
 int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c)
@@ -31,15 +31,23 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     c->wavelet = wavelet;
     c->norm = DWT2_NORM_UNIT_DC;
     c->scheme = DWT2_SCHEME_AUTO;
+    c->arithmetic = DWT2_ARITH_AUTO;
     if (opt) {
         for (int r : opt->reserved)
             if (r != 0) return DWT2_E_ARG;
         c->norm = opt->norm;
         c->scheme = opt->scheme;
+        c->arithmetic = opt->arithmetic;
     }
+    if (c->arithmetic < DWT2_ARITH_AUTO || c->arithmetic > DWT2_ARITH_FP64) return DWT2_E_UNSUPPORTED;
     if (c->norm != DWT2_NORM_UNIT_DC && c->norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
-    if (c->scheme < DWT2_SCHEME_AUTO || c->scheme > DWT2_SCHEME_ROWCOL) return DWT2_E_UNSUPPORTED;
+    if (c->scheme < DWT2_SCHEME_AUTO || c->scheme > DWT2_SCHEME_MONOLITHIC_STAR_TILE)
+        return DWT2_E_UNSUPPORTED;
     if (c->scheme == DWT2_SCHEME_AUTO) c->scheme = DWT2_SCHEME_MONOLITHIC_STAR;
+    // FP64 lifting is implemented by the fused kernel only.
+    if (c->arithmetic == DWT2_ARITH_FP64 && c->scheme != DWT2_SCHEME_MONOLITHIC_STAR)
+        return DWT2_E_UNSUPPORTED;
+    if (c->arithmetic == DWT2_ARITH_AUTO) c->arithmetic = DWT2_ARITH_FP32;
     return DWT2_OK;
 }
 
@@ -171,7 +179,7 @@ DWT2_EXPORT const char *dwt2_status_string(int status)
     case DWT2_OK: return "ok";
     case DWT2_E_ARG: return "invalid argument";
     case DWT2_E_SIZE: return "a level's input is smaller than 2x2";
-    case DWT2_E_UNSUPPORTED: return "unsupported wavelet, extension, normalisation or scheme";
+    case DWT2_E_UNSUPPORTED: return "unsupported wavelet, extension, normalisation, scheme or arithmetic";
     case DWT2_E_WORKSPACE: return "workspace missing or too small";
     case DWT2_E_ALIAS: return "src, dst or workspace overlap";
     case DWT2_E_HIP: return "HIP launch failed";
@@ -227,9 +235,13 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
             a.ll = buf[k & 1];
             a.ll_pitch = (W + 1) / 2;
         }
-        hipError_t e = c.cfg.scheme == DWT2_SCHEME_ROWCOL
-                           ? dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, W, stream)
-                           : dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
+        hipError_t e;
+        if (c.cfg.scheme == DWT2_SCHEME_ROWCOL)
+            e = dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, W, stream);
+        else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
+            e = dwt2::launch_fused_forward(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64, a, stream);
+        else
+            e = dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
         if (e != hipSuccess) return hip_status(e);
         in = a.ll;
         in_pitch = a.ll_pitch;
@@ -274,9 +286,13 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
             a.out = buf[(k - 1) & 1];
             a.out_pitch = W;
         }
-        hipError_t e = c.cfg.scheme == DWT2_SCHEME_ROWCOL
-                           ? dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, W, stream)
-                           : dwt2::launch_tile_inverse(c.cfg.wavelet, c.cfg.scheme, a, stream);
+        hipError_t e;
+        if (c.cfg.scheme == DWT2_SCHEME_ROWCOL)
+            e = dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, W, stream);
+        else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
+            e = dwt2::launch_fused_inverse(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64, a, stream);
+        else
+            e = dwt2::launch_tile_inverse(c.cfg.wavelet, c.cfg.scheme, a, stream);
         if (e != hipSuccess) return hip_status(e);
         ll = a.out;
         ll_pitch = a.out_pitch;

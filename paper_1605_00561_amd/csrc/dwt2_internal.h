@@ -8,7 +8,9 @@
 namespace dwt2 {
 
 enum Wavelet : int { CDF53 = 0, CDF97 = 1 };
-enum Scheme : int { MONO_STAR = 1, SWELDENS = 2, IWAHASHI = 3, ROWCOL = 4 };
+// Scheme ids as in dwt2.h; MONO_STAR is the fused register-blocked kernel and
+// MONO_STAR_TILE the same steps in the LDS tile harness.
+enum Scheme : int { MONO_STAR = 1, SWELDENS = 2, IWAHASHI = 3, ROWCOL = 4, MONO_STAR_TILE = 5 };
 
 // Lifting pairs in the L = x[2n], H = x[2n+1] phase.  The paper's operators
 // (Sec. 5) P(z) = p (1 + z^-1) and U(z) = u (1 + z) become, after the index
@@ -106,6 +108,11 @@ inline hipError_t launch(void (*kern)(Args...), dim3 grid, dim3 block, hipStream
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_tile_forward(int wavelet, int scheme, const FwdArgs &a, hipStream_t s);
 hipError_t launch_tile_inverse(int wavelet, int scheme, const InvArgs &a, hipStream_t s);
+
+// Fused Monolithic* (registers + DPP, LDS only at wavefront seams).
+// fp64: lift in double-precision registers (samples stay FP32 in memory).
+hipError_t launch_fused_forward(int wavelet, bool fp64, const FwdArgs &a, hipStream_t s);
+hipError_t launch_fused_inverse(int wavelet, bool fp64, const InvArgs &a, hipStream_t s);
 
 // Row-column: the intermediate `tmp` is W x H with pitch tmp_pitch.
 hipError_t launch_rowcol_forward(int wavelet, const FwdArgs &a, float *tmp, ptrdiff_t tmp_pitch,

@@ -1,0 +1,519 @@
+// fused_kernels.hip -- the fused Monolithic* level kernels for gfx950.
+//
+// Scheme (Sec. 4, "Improvements"), per lifting pair:
+//   barrier | T_{P1}, then the scalar T^H_{P0}, T^V_{P0}   (spatial predict)
+//   barrier | S_{U1}, then the scalar S^H_{U0}, S^V_{U0}   (spatial update)
+// The inverse undoes each pair in reverse: the scalar update parts, S_{-U1}
+// (barrier), the scalar predict parts, T_{-P1} (barrier).
+//
+// Mapping.  A work-group owns one overlapping tile of 64 x (NW * RB)
+// quadruples (K quadruples of halo per side, K = lifting pairs), as in the
+// paper's block-based method (Sec. 6).  Lane c of wavefront w holds the
+// quadruples of column c, rows w*RB .. w*RB + RB - 1, in registers:
+//   * horizontal neighbours (c +- 1) are read from the adjacent lane with DPP
+//     wave shifts, which need no barrier (a wavefront runs in lockstep);
+//   * vertical neighbours inside a wavefront's run are registers: the predict
+//     walks the rows downwards and reads the row below before it is
+//     predicted, the update walks upwards and reads the row above before it
+//     is updated, so every neighbour read sees the pre-step value;
+//   * only the rows at the seams between wavefronts go through LDS: before a
+//     step each wavefront publishes the one row its neighbour needs, and the
+//     work-group barrier that the scheme places before the step makes it
+//     visible.  Two seam buffers alternate between predict and update, so
+//     Monolithic* keeps its two barriers per lifting pair.
+// LDS is a few KB, so occupancy is set by registers, not LDS.
+//
+// Borders: whole-sample symmetric extension, samples read from mirrored
+// positions.  Centring: each tile subtracts the rounded mean c of its middle
+// quadruple row and adds c * ll_gain back to LL (exact by linearity).
+// Tiles are numbered so that each XCD (work-group id mod 8) takes a
+// contiguous row-major run, so neighbouring tiles share their halo in L2.
+#include "dwt2_internal.h"
+
+namespace dwt2 {
+namespace {
+
+constexpr int TX = 64;  // quadruple columns per tile (one per lane)
+constexpr int NW = 4;   // wavefronts per work-group
+constexpr int RB = 7;   // quadruple rows per wavefront
+constexpr int TY = NW * RB;
+constexpr int NTHREADS = TX * NW;
+constexpr int SP = TX + 2;  // seam row stride: one padding cell each side
+
+enum { LL = 0, HL = 1, LH = 2, HH = 3 };
+
+// DPP wave shifts: wave_shl:1 gives lane i the value of lane i+1, wave_shr:1
+// that of lane i-1; the end lane gets 0 (it holds a halo column).
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+__device__ __forceinline__ float from_right(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_WAVE_SHL1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_left(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_WAVE_SHR1, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ double from_right(double v)
+{
+    const int2 b = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(
+        double, make_int2(__builtin_amdgcn_update_dpp(0, b.x, DPP_WAVE_SHL1, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, b.y, DPP_WAVE_SHL1, 0xf, 0xf, false)));
+}
+__device__ __forceinline__ double from_left(double v)
+{
+    const int2 b = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(
+        double, make_int2(__builtin_amdgcn_update_dpp(0, b.x, DPP_WAVE_SHR1, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, b.y, DPP_WAVE_SHR1, 0xf, 0xf, false)));
+}
+
+// Fused multiply-add in the arithmetic type of the kernel.
+__device__ __forceinline__ float mad(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double mad(double a, double b, double c) { return fma(a, b, c); }
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int xcd_tile(int ntiles)
+{
+    const int per = gridDim.x >> 3;  // grid is a multiple of 8
+    const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    return t < ntiles ? t : -1;
+}
+
+// Seam buffers: [buffer][component][wavefront][lane + 1].
+template <typename T>
+struct Seams {
+    T v[2][2][NW + 1][SP];
+};
+
+template <typename T>
+__device__ __forceinline__ T &seam(Seams<T> &s, int b, int comp, int w, int c)
+{
+    return s.v[b][comp][w][c + 1];
+}
+
+// T_{P1} then T^H_{P0}, T^V_{P0} on one quadruple (neighbours pre-step).
+template <typename T>
+__device__ __forceinline__ void predict_q(T (&q)[4], T llr, T lld, T lldr, T hld, T lhr, T p, T p2)
+{
+    T &ll = q[LL], &hl = q[HL], &lh = q[LH], &hh = q[HH];
+    hl = mad(p, llr, hl);
+    lh = mad(p, lld, lh);
+    hh = mad(p2, lldr, mad(p, hld, mad(p, lhr, hh)));
+    hl = mad(p, ll, hl);
+    hh = mad(p, lh, hh);
+    lh = mad(p, ll, lh);
+    hh = mad(p, hl, hh);
+}
+
+// S_{U1} then S^H_{U0}, S^V_{U0} on one quadruple (neighbours pre-step).
+template <typename T>
+__device__ __forceinline__ void update_q(T (&q)[4], T hll, T lhu, T hhul, T hhu, T hhl, T u, T u2)
+{
+    T &ll = q[LL], &hl = q[HL], &lh = q[LH], &hh = q[HH];
+    ll = mad(u, hll, mad(u, lhu, mad(u2, hhul, ll)));
+    hl = mad(u, hhu, hl);
+    lh = mad(u, hhl, lh);
+    ll = mad(u, hl, ll);
+    lh = mad(u, hh, lh);
+    ll = mad(u, lh, ll);
+    hl = mad(u, hh, hl);
+}
+
+// T_{-P1} on one quadruple.
+template <typename T>
+__device__ __forceinline__ void unpredict_q(T (&q)[4], T llr, T lld, T lldr, T hld, T lhr, T p, T p2)
+{
+    q[HL] = mad(-p, llr, q[HL]);
+    q[LH] = mad(-p, lld, q[LH]);
+    q[HH] = mad(p2, lldr, mad(-p, hld, mad(-p, lhr, q[HH])));
+}
+
+// S_{-U1} on one quadruple.
+template <typename T>
+__device__ __forceinline__ void unupdate_q(T (&q)[4], T hll, T lhu, T hhul, T hhu, T hhl, T u, T u2)
+{
+    q[LL] = mad(-u, hll, mad(-u, lhu, mad(u2, hhul, q[LL])));
+    q[HL] = mad(-u, hhu, q[HL]);
+    q[LH] = mad(-u, hhl, q[LH]);
+}
+
+// Neighbour part of a predict step over the wavefront's run, rows downwards.
+// Row RB-1 reads the first row of the next wavefront from seam buffer b.
+template <bool INV, typename T>
+__device__ __forceinline__ void predict_run(T (&q)[RB][4], Seams<T> &sm, int b, int w, int lane, T p)
+{
+    const T p2 = p * p;
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        T lld, hld, lldr;
+        if (j + 1 < RB) {
+            lld = q[j + 1][LL];
+            hld = q[j + 1][HL];
+            lldr = from_right(lld);
+        } else {
+            lld = seam(sm, b, 0, w + 1, lane);
+            hld = seam(sm, b, 1, w + 1, lane);
+            lldr = seam(sm, b, 0, w + 1, lane + 1);
+        }
+        const T llr = from_right(q[j][LL]);
+        const T lhr = from_right(q[j][LH]);
+        if (!INV)
+            predict_q(q[j], llr, lld, lldr, hld, lhr, p, p2);
+        else
+            unpredict_q(q[j], llr, lld, lldr, hld, lhr, p, p2);
+    }
+}
+
+// Neighbour part of an update step over the run, rows upwards.  Row 0 reads
+// the last row of the previous wavefront from seam buffer b.
+template <bool INV, typename T>
+__device__ __forceinline__ void update_run(T (&q)[RB][4], Seams<T> &sm, int b, int w, int lane, T u)
+{
+    const T u2 = u * u;
+#pragma unroll
+    for (int j = RB - 1; j >= 0; j--) {
+        T lhu, hhu, hhul;
+        if (j > 0) {
+            lhu = q[j - 1][LH];
+            hhu = q[j - 1][HH];
+            hhul = from_left(hhu);
+        } else {
+            lhu = seam(sm, b, 0, w - 1 + 1, lane);   // row above: stored at index w
+            hhu = seam(sm, b, 1, w - 1 + 1, lane);
+            hhul = seam(sm, b, 1, w - 1 + 1, lane - 1);
+        }
+        const T hll = from_left(q[j][HL]);
+        const T hhl = from_left(q[j][HH]);
+        if (!INV)
+            update_q(q[j], hll, lhu, hhul, hhu, hhl, u, u2);
+        else
+            unupdate_q(q[j], hll, lhu, hhul, hhu, hhl, u, u2);
+    }
+}
+
+// Seam layout: a predict buffer holds the first row (LL, HL) of wavefront w
+// at index w; an update buffer holds the last row (LH, HH) of wavefront w at
+// index w + 1, so a wavefront reads its upper neighbour at its own index.
+template <typename T>
+__device__ __forceinline__ void publish_first(T (&q)[RB][4], Seams<T> &sm, int b, int w, int lane)
+{
+    seam(sm, b, 0, w, lane) = q[0][LL];
+    seam(sm, b, 1, w, lane) = q[0][HL];
+}
+template <typename T>
+__device__ __forceinline__ void publish_last(T (&q)[RB][4], Seams<T> &sm, int b, int w, int lane)
+{
+    seam(sm, b, 0, w + 1, lane) = q[RB - 1][LH];
+    seam(sm, b, 1, w + 1, lane) = q[RB - 1][HH];
+}
+
+template <typename T>
+__device__ __forceinline__ void scalar_predict(T (&q)[RB][4], T p)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        q[j][HL] = mad(p, q[j][LL], q[j][HL]);  // T^H_{P0}
+        q[j][HH] = mad(p, q[j][LH], q[j][HH]);
+        q[j][LH] = mad(p, q[j][LL], q[j][LH]);  // T^V_{P0}
+        q[j][HH] = mad(p, q[j][HL], q[j][HH]);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void scalar_update(T (&q)[RB][4], T u)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        q[j][LL] = mad(u, q[j][HL], q[j][LL]);  // S^H_{U0}
+        q[j][LH] = mad(u, q[j][HH], q[j][LH]);
+        q[j][LL] = mad(u, q[j][LH], q[j][LL]);  // S^V_{U0}
+        q[j][HL] = mad(u, q[j][HH], q[j][HL]);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void scalar_unupdate(T (&q)[RB][4], T u)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        q[j][LL] = mad(-u, q[j][LH], q[j][LL]);  // undo S^V_{U0}
+        q[j][HL] = mad(-u, q[j][HH], q[j][HL]);
+        q[j][LL] = mad(-u, q[j][HL], q[j][LL]);  // undo S^H_{U0}
+        q[j][LH] = mad(-u, q[j][HH], q[j][LH]);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void scalar_unpredict(T (&q)[RB][4], T p)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        q[j][HH] = mad(-p, q[j][HL], q[j][HH]);  // undo T^V_{P0}
+        q[j][LH] = mad(-p, q[j][LL], q[j][LH]);
+        q[j][HH] = mad(-p, q[j][LH], q[j][HH]);  // undo T^H_{P0}
+        q[j][HL] = mad(-p, q[j][LL], q[j][HL]);
+    }
+}
+
+// Lifting constants in the arithmetic type: FP32 literals, or for FP64 the
+// same values written to double precision.
+template <int WAV, typename T>
+struct Coef {
+    __device__ static T p(int k) { return Lift<WAV>::p(k); }
+    __device__ static T u(int k) { return Lift<WAV>::u(k); }
+};
+template <>
+struct Coef<CDF97, double> {
+    __device__ static double p(int k) { return k == 0 ? -1.58613434205992355842832 : 0.88291107553093329591979; }
+    __device__ static double u(int k) { return k == 0 ? -0.0529801185729614146241296 : 0.443506852043971152115604; }
+};
+
+template <int WAV, typename T>
+__device__ __forceinline__ void forward_tile(T (&q)[RB][4], Seams<T> &sm, int w, int lane)
+{
+    using C = Coef<WAV, T>;
+#pragma unroll
+    for (int k = 0; k < Lift<WAV>::K; k++) {
+        publish_first(q, sm, 0, w, lane);
+        __syncthreads();
+        predict_run<false>(q, sm, 0, w, lane, C::p(k));
+        scalar_predict(q, C::p(k));
+        publish_last(q, sm, 1, w, lane);
+        __syncthreads();
+        update_run<false>(q, sm, 1, w, lane, C::u(k));
+        scalar_update(q, C::u(k));
+    }
+}
+
+template <int WAV, typename T>
+__device__ __forceinline__ void inverse_tile(T (&q)[RB][4], Seams<T> &sm, int w, int lane)
+{
+    using C = Coef<WAV, T>;
+#pragma unroll
+    for (int kk = 0; kk < Lift<WAV>::K; kk++) {
+        const int k = Lift<WAV>::K - 1 - kk;
+        scalar_unupdate(q, C::u(k));
+        publish_last(q, sm, 1, w, lane);
+        __syncthreads();
+        update_run<true>(q, sm, 1, w, lane, C::u(k));
+        scalar_unpredict(q, C::p(k));
+        publish_first(q, sm, 0, w, lane);
+        __syncthreads();
+        predict_run<true>(q, sm, 0, w, lane, C::p(k));
+    }
+}
+
+__device__ __forceinline__ void store_nt(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_nt2(float *p, float a, float b)
+{
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2 v = {a, b};
+    __builtin_nontemporal_store(v, (f2 *)p);
+}
+
+// Horizontal fast path: the tile's 128 pixel columns lie inside the image and
+// rows are 8-byte aligned, so each pixel-row pair is one float2 per lane.
+template <int WAV, typename T, bool VEC>
+__device__ __forceinline__ void fwd_body(const FwdArgs &a, Seams<T> &sm, int tc, int tr, int w, int lane)
+{
+    constexpr int HQ = Lift<WAV>::K;
+    constexpr int IX = TX - 2 * HQ, IY = TY - 2 * HQ;
+    const int W = a.W, H = a.H;
+    const int QW = (W + 1) >> 1, QH = (H + 1) >> 1, WH = W >> 1, HHr = H >> 1;
+    const int qc = tc * IX - HQ + lane;
+    const int x0 = ws_mirror(2 * qc, W), x1 = ws_mirror(2 * qc + 1, W);
+    const int qr0 = tr * IY - HQ + w * RB;
+
+    T q[RB][4];
+    auto load = [&](int qr, float &ll, float &hl, float &lh, float &hh) {
+        const float *r0 = a.in + (ptrdiff_t)ws_mirror(2 * qr, H) * a.in_pitch;
+        const float *r1 = a.in + (ptrdiff_t)ws_mirror(2 * qr + 1, H) * a.in_pitch;
+        if constexpr (VEC) {
+            const float2 e = *(const float2 *)(r0 + 2 * qc), o = *(const float2 *)(r1 + 2 * qc);
+            ll = e.x; hl = e.y; lh = o.x; hh = o.y;
+        } else {
+            ll = r0[x0]; hl = r0[x1]; lh = r1[x0]; hh = r1[x1];
+        }
+    };
+    float raw[RB][4];
+#pragma unroll
+    for (int j = 0; j < RB; j++) load(qr0 + j, raw[j][LL], raw[j][HL], raw[j][LH], raw[j][HH]);
+    float c;
+    {
+        float a0, a1, a2, a3;
+        load(tr * IY - HQ + TY / 2, a0, a1, a2, a3);
+        const float sum = wave_sum((a0 + a1) + (a2 + a3));
+        c = rintf(sum * (1.0f / (4 * TX)) / a.quantum) * a.quantum;
+    }
+#pragma unroll
+    for (int j = 0; j < RB; j++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) q[j][e] = (T)raw[j][e] - (T)c;
+
+    forward_tile<WAV>(q, sm, w, lane);
+
+    if (lane < HQ || lane >= TX - HQ || qc >= QW) return;
+    const float cll = c * a.ll_gain;
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        const int r = w * RB + j, qr = qr0 + j;
+        if (r < HQ || r >= TY - HQ || qr >= QH) continue;
+        store_nt(a.ll + (ptrdiff_t)qr * a.ll_pitch + qc,
+                 (float)(q[j][LL] * (T)a.s.ll + (T)cll));
+        float *drow = a.det + (ptrdiff_t)qr * a.det_pitch;
+        if (qc < WH) store_nt(drow + QW + qc, (float)q[j][HL]);
+        if (qr < HHr) {
+            float *hrow = a.det + (ptrdiff_t)(QH + qr) * a.det_pitch;
+            store_nt(hrow + qc, (float)q[j][LH]);
+            if (qc < WH) store_nt(hrow + QW + qc, (float)(q[j][HH] * (T)a.s.hh));
+        }
+    }
+}
+
+template <int WAV, typename T, bool VEC>
+__device__ __forceinline__ void inv_body(const InvArgs &a, Seams<T> &sm, int tc, int tr, int w, int lane)
+{
+    constexpr int HQ = Lift<WAV>::K;
+    constexpr int IX = TX - 2 * HQ, IY = TY - 2 * HQ;
+    const int W = a.W, H = a.H;
+    const int QW = (W + 1) >> 1, QH = (H + 1) >> 1;
+    const int qc = tc * IX - HQ + lane;
+    const int cl = ws_mirror(2 * qc, W) >> 1, ch = ws_mirror(2 * qc + 1, W) >> 1;
+    const int qr0 = tr * IY - HQ + w * RB;
+
+    float c;
+    {
+        const int rm = ws_mirror(2 * (tr * IY - HQ + TY / 2), H) >> 1;
+        const float sum = wave_sum(a.ll[(ptrdiff_t)rm * a.ll_pitch + cl]);
+        c = rintf(sum * (1.0f / TX) / (a.ll_gain * a.quantum)) * a.quantum;
+    }
+    const float cll = c * a.ll_gain;
+
+    T q[RB][4];
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        const int qr = qr0 + j;
+        const int rl = ws_mirror(2 * qr, H) >> 1, rh = ws_mirror(2 * qr + 1, H) >> 1;
+        const float *lrow = a.det + (ptrdiff_t)rl * a.det_pitch;
+        const float *hrow = a.det + (ptrdiff_t)(QH + rh) * a.det_pitch;
+        q[j][LL] = ((T)a.ll[(ptrdiff_t)rl * a.ll_pitch + cl] - (T)cll) * (T)a.inv_s.ll;
+        q[j][HL] = lrow[QW + ch];
+        q[j][LH] = hrow[cl];
+        q[j][HH] = (T)hrow[QW + ch] * (T)a.inv_s.hh;
+    }
+
+    inverse_tile<WAV>(q, sm, w, lane);
+
+    if (lane < HQ || lane >= TX - HQ || qc >= QW) return;
+    const int px = 2 * qc;
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        const int r = w * RB + j, qr = qr0 + j;
+        if (r < HQ || r >= TY - HQ || qr >= QH) continue;
+        float *o0 = a.out + (ptrdiff_t)(2 * qr) * a.out_pitch;
+        const T cc = c;
+        const float v0 = (float)(q[j][LL] + cc), v1 = (float)(q[j][HL] + cc);
+        const float v2 = (float)(q[j][LH] + cc), v3 = (float)(q[j][HH] + cc);
+        if (VEC) {
+            store_nt2(o0 + px, v0, v1);
+            if (2 * qr + 1 < H) store_nt2(o0 + a.out_pitch + px, v2, v3);
+        } else {
+            store_nt(o0 + px, v0);
+            if (px + 1 < W) store_nt(o0 + px + 1, v1);
+            if (2 * qr + 1 < H) {
+                store_nt(o0 + a.out_pitch + px, v2);
+                if (px + 1 < W) store_nt(o0 + a.out_pitch + px + 1, v3);
+            }
+        }
+    }
+}
+
+template <int WAV, typename T>
+__global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, int ntiles)
+{
+    constexpr int HQ = Lift<WAV>::K;
+    __shared__ Seams<T> sm;
+    const int tile = xcd_tile(ntiles);
+    if (tile < 0) return;  // uniform over the work-group
+    const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
+    const int tc = tile % ntx, tr = tile / ntx;
+    const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+    const bool vec = px_first >= 0 && px_first + 2 * TX <= a.W &&
+                     (((uintptr_t)a.in | (uintptr_t)(a.in_pitch * 4)) & 7) == 0;
+    if (vec)
+        fwd_body<WAV, T, true>(a, sm, tc, tr, w, lane);
+    else
+        fwd_body<WAV, T, false>(a, sm, tc, tr, w, lane);
+}
+
+template <int WAV, typename T>
+__global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, int ntiles)
+{
+    constexpr int HQ = Lift<WAV>::K;
+    __shared__ Seams<T> sm;
+    const int tile = xcd_tile(ntiles);
+    if (tile < 0) return;
+    const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
+    const int tc = tile % ntx, tr = tile / ntx;
+    const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+    const bool vec = px_first >= 0 && px_first + 2 * TX <= a.W &&
+                     (((uintptr_t)a.out | (uintptr_t)(a.out_pitch * 4)) & 7) == 0;
+    if (vec)
+        inv_body<WAV, T, true>(a, sm, tc, tr, w, lane);
+    else
+        inv_body<WAV, T, false>(a, sm, tc, tr, w, lane);
+}
+
+struct Grid {
+    int ntx, ntiles, blocks;
+};
+
+Grid fused_grid(int W, int H, int HQ)
+{
+    const int QW = (W + 1) / 2, QH = (H + 1) / 2;
+    const int ix = TX - 2 * HQ, iy = TY - 2 * HQ;
+    Grid g;
+    g.ntx = (QW + ix - 1) / ix;
+    g.ntiles = g.ntx * ((QH + iy - 1) / iy);
+    g.blocks = (g.ntiles + 7) / 8 * 8;
+    return g;
+}
+
+}  // namespace
+
+hipError_t launch_fused_forward(int wavelet, bool fp64, const FwdArgs &a, hipStream_t s)
+{
+    const int HQ = wavelet == CDF97 ? 2 : 1;
+    const Grid g = fused_grid(a.W, a.H, HQ);
+    const dim3 grid(g.blocks), block(NTHREADS);
+    if (wavelet == CDF53)
+        return fp64 ? launch(k_fused_forward<CDF53, double>, grid, block, s, a, g.ntx, g.ntiles)
+                    : launch(k_fused_forward<CDF53, float>, grid, block, s, a, g.ntx, g.ntiles);
+    if (wavelet == CDF97)
+        return fp64 ? launch(k_fused_forward<CDF97, double>, grid, block, s, a, g.ntx, g.ntiles)
+                    : launch(k_fused_forward<CDF97, float>, grid, block, s, a, g.ntx, g.ntiles);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused_inverse(int wavelet, bool fp64, const InvArgs &a, hipStream_t s)
+{
+    const int HQ = wavelet == CDF97 ? 2 : 1;
+    const Grid g = fused_grid(a.W, a.H, HQ);
+    const dim3 grid(g.blocks), block(NTHREADS);
+    if (wavelet == CDF53)
+        return fp64 ? launch(k_fused_inverse<CDF53, double>, grid, block, s, a, g.ntx, g.ntiles)
+                    : launch(k_fused_inverse<CDF53, float>, grid, block, s, a, g.ntx, g.ntiles);
+    if (wavelet == CDF97)
+        return fp64 ? launch(k_fused_inverse<CDF97, double>, grid, block, s, a, g.ntx, g.ntiles)
+                    : launch(k_fused_inverse<CDF97, float>, grid, block, s, a, g.ntx, g.ntiles);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace dwt2

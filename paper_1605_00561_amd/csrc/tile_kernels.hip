@@ -10,6 +10,7 @@
 // one barrier:
 //
 //   Monolithic*  (Sec. 4)  T_{P1}+T^H_{P0}+T^V_{P0} | S_{U1}+S^H_{U0}+S^V_{U0}
+//   (this tile form; the default fused kernel is the streaming one)
 //                          2 barriers per pair, 6 LDS cells per quadruple
 //   Sweldens     (Sec. 2)  T^H_P | T^V_P | S^H_U | S^V_U
 //                          4 barriers per pair, 4 LDS cells
@@ -284,7 +285,7 @@ __device__ __forceinline__ void transform_tile(float *lds, Quads &q, int lane, i
     int step = 0;
     auto buf = [&]() { return (step++ & 1) * BUF; };
 #define SYNC() __syncthreads()
-    if constexpr (SCH == MONO_STAR) {
+    if constexpr (SCH == MONO_STAR_TILE) {
 #pragma unroll
         for (int kk = 0; kk < L::K; kk++) {
             const int k = INV ? L::K - 1 - kk : kk;
@@ -535,11 +536,11 @@ hipError_t inv(const InvArgs &a, hipStream_t s)
 hipError_t launch_tile_forward(int wavelet, int scheme, const FwdArgs &a, hipStream_t s)
 {
     if (wavelet == CDF53) {
-        if (scheme == MONO_STAR) return fwd<CDF53, MONO_STAR>(a, s);
+        if (scheme == MONO_STAR_TILE) return fwd<CDF53, MONO_STAR_TILE>(a, s);
         if (scheme == SWELDENS) return fwd<CDF53, SWELDENS>(a, s);
         if (scheme == IWAHASHI) return fwd<CDF53, IWAHASHI>(a, s);
     } else if (wavelet == CDF97) {
-        if (scheme == MONO_STAR) return fwd<CDF97, MONO_STAR>(a, s);
+        if (scheme == MONO_STAR_TILE) return fwd<CDF97, MONO_STAR_TILE>(a, s);
         if (scheme == SWELDENS) return fwd<CDF97, SWELDENS>(a, s);
         if (scheme == IWAHASHI) return fwd<CDF97, IWAHASHI>(a, s);
     }
@@ -549,11 +550,11 @@ hipError_t launch_tile_forward(int wavelet, int scheme, const FwdArgs &a, hipStr
 hipError_t launch_tile_inverse(int wavelet, int scheme, const InvArgs &a, hipStream_t s)
 {
     if (wavelet == CDF53) {
-        if (scheme == MONO_STAR) return inv<CDF53, MONO_STAR>(a, s);
+        if (scheme == MONO_STAR_TILE) return inv<CDF53, MONO_STAR_TILE>(a, s);
         if (scheme == SWELDENS) return inv<CDF53, SWELDENS>(a, s);
         if (scheme == IWAHASHI) return inv<CDF53, IWAHASHI>(a, s);
     } else if (wavelet == CDF97) {
-        if (scheme == MONO_STAR) return inv<CDF97, MONO_STAR>(a, s);
+        if (scheme == MONO_STAR_TILE) return inv<CDF97, MONO_STAR_TILE>(a, s);
         if (scheme == SWELDENS) return inv<CDF97, SWELDENS>(a, s);
         if (scheme == IWAHASHI) return inv<CDF97, IWAHASHI>(a, s);
     }

@@ -20,21 +20,28 @@ CDF53, CDF97 = 0, 1
 EXT_WHOLE_SYMMETRIC = 0
 NORM_UNIT_DC, NORM_PAPER = 0, 1
 SCHEME_AUTO, SCHEME_MONOLITHIC_STAR, SCHEME_SWELDENS, SCHEME_IWAHASHI, SCHEME_ROWCOL = 0, 1, 2, 3, 4
+SCHEME_MONOLITHIC_STAR_TILE = 5
 
 WAVELETS = {"cdf53": CDF53, "cdf97": CDF97, CDF53: CDF53, CDF97: CDF97}
 NORMS = {"unit_dc": NORM_UNIT_DC, "paper": NORM_PAPER, NORM_UNIT_DC: NORM_UNIT_DC,
          NORM_PAPER: NORM_PAPER}
 SCHEMES = {"auto": SCHEME_AUTO, "monolithic*": SCHEME_MONOLITHIC_STAR,
-           "sweldens": SCHEME_SWELDENS, "iwahashi": SCHEME_IWAHASHI, "rowcol": SCHEME_ROWCOL}
+           "monolithic*-tile": SCHEME_MONOLITHIC_STAR_TILE, "sweldens": SCHEME_SWELDENS,
+           "iwahashi": SCHEME_IWAHASHI, "rowcol": SCHEME_ROWCOL}
 SCHEMES.update({v: v for v in list(SCHEMES.values())})
 
 EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_string",
            "dwt2_last_hip_error", "dwt2_version"]
 
 
+ARITH_AUTO, ARITH_FP32, ARITH_FP64 = 0, 1, 2
+ARITHS = {"auto": ARITH_AUTO, "fp32": ARITH_FP32, "fp64": ARITH_FP64,
+          ARITH_AUTO: ARITH_AUTO, ARITH_FP32: ARITH_FP32, ARITH_FP64: ARITH_FP64}
+
+
 class Options(ctypes.Structure):
-    _fields_ = [("norm", ctypes.c_int), ("scheme", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+    _fields_ = [("norm", ctypes.c_int), ("scheme", ctypes.c_int), ("arithmetic", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 class Dwt2Error(RuntimeError):
@@ -81,10 +88,11 @@ def library() -> ctypes.CDLL:
     return _lib
 
 
-def make_options(norm="unit_dc", scheme="auto") -> Options:
+def make_options(norm="unit_dc", scheme="auto", arithmetic="auto") -> Options:
     o = Options()
     o.norm = NORMS[norm]
     o.scheme = SCHEMES[scheme]
+    o.arithmetic = ARITHS[arithmetic]
     return o
 
 
@@ -153,7 +161,7 @@ def _stream_handle(stream):
 
 
 def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
-            workspace=None, stream=None):
+            workspace=None, stream=None, arithmetic="auto"):
     """Forward DWT of a (H, W) float32 device tensor; returns the Mallat layout."""
     import torch
     _check_image(img)
@@ -161,7 +169,7 @@ def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=N
     if out is None:
         out = torch.empty((h, w), dtype=torch.float32, device=img.device)
     _check_image(out)
-    opt = make_options(norm, scheme)
+    opt = make_options(norm, scheme, arithmetic)
     ws, nws = _workspace(wavelet, levels, w, h, opt, img.device, workspace)
     st = dwt2_forward(wavelet, levels, w, h, img.data_ptr(), img.stride(0), out.data_ptr(),
                       out.stride(0), EXT_WHOLE_SYMMETRIC, opt,
@@ -172,7 +180,7 @@ def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=N
 
 
 def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
-            workspace=None, stream=None):
+            workspace=None, stream=None, arithmetic="auto"):
     """Inverse DWT of a (H, W) Mallat-layout float32 device tensor; returns the image."""
     import torch
     _check_image(coef)
@@ -180,7 +188,7 @@ def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=
     if out is None:
         out = torch.empty((h, w), dtype=torch.float32, device=coef.device)
     _check_image(out)
-    opt = make_options(norm, scheme)
+    opt = make_options(norm, scheme, arithmetic)
     ws, nws = _workspace(wavelet, levels, w, h, opt, coef.device, workspace)
     st = dwt2_inverse(wavelet, levels, w, h, coef.data_ptr(), coef.stride(0), out.data_ptr(),
                       out.stride(0), EXT_WHOLE_SYMMETRIC, opt,

@@ -96,7 +96,7 @@ def test_argument_errors():
     assert _fwd(dst_pitch=8) == dwt2.E_ARG
     assert _fwd(src=FAKE + 2) == dwt2.E_ARG  # not 4-byte aligned
     o = dwt2.make_options()
-    o.reserved[3] = 1
+    o.reserved[2] = 1
     assert _fwd(opt=o) == dwt2.E_ARG
 
 
@@ -114,8 +114,13 @@ def test_unsupported():
     o.norm = 2
     assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
     o = dwt2.make_options()
-    o.scheme = 9
+    o.scheme = 6
     assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
+    o = dwt2.make_options()
+    o.arithmetic = 3
+    assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
+    for scheme in ("monolithic*-tile", "sweldens", "iwahashi", "rowcol"):
+        assert _fwd(opt=dwt2.make_options(scheme=scheme, arithmetic="fp64")) == dwt2.E_UNSUPPORTED
 
 
 def test_workspace_and_alias_errors():
