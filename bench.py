@@ -46,6 +46,8 @@ def parse():
                     help="approximate CPU time budget for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-schemes", action="store_true")
+    ap.add_argument("--no-pyramid", action="store_true",
+                    help="skip the per-level table of the 16384^2 five-level workload")
     ap.add_argument("--no-copy", action="store_true",
                     help="skip the device-to-device copy (the bandwidth and counter reference)")
     return ap.parse_args()
@@ -148,6 +150,10 @@ def main():
 
     if not args.no_schemes:
         out["schemes"] = scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, args.scheme_reps)
+    if not args.no_pyramid:
+        del xs, ys, zs
+        torch.cuda.empty_cache()
+        out["pyramid"] = pyramid_table(dwt2, torch, workloads, args.scheme_reps)
     if not args.no_copy:
         out["copy_GBs"] = copy_bandwidth(torch, dev)
 
@@ -192,6 +198,60 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
         table[name] = res
     return table
+
+
+def _median_us(torch, fn, reps):
+    stream = torch.cuda.current_stream()
+    fn(0)
+    ev = []
+    for i in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(i)
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    return statistics.median(a.elapsed_time(b) for a, b in ev) * 1e3
+
+
+def pyramid_table(dwt2, torch, workloads, reps):
+    """Per-level forward and inverse of the fused kernel on the 16384^2 CDF 9/7
+    five-level workload: each level's input size timed as a one-level call on
+    the LL band the previous level produced, plus the whole five-level call."""
+    name = "cdf97_16384_l5"
+    spec = workloads.WORKLOADS[name]
+    W, H, wav, lev = spec["width"], spec["height"], spec["wavelet"], spec["levels"]
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(workloads.workload_image(name)).to(dev)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    levels = []
+    cur = x
+    w, h = W, H
+    for k in range(lev):
+        src = cur.contiguous()
+        dst = torch.empty_like(src)
+        back = torch.empty_like(src)
+        tf = _median_us(torch, lambda i: dwt2.forward(src, wav, 1, out=dst), reps)
+        ti = _median_us(torch, lambda i: dwt2.inverse(dst, wav, 1, out=back), reps)
+        npx = w * h
+        levels.append({"level": k + 1, "width": w, "height": h,
+                       "forward_us": round(tf, 2), "inverse_us": round(ti, 2),
+                       "forward_Gpixel_s": round(npx / tf / 1e3, 1),
+                       "inverse_Gpixel_s": round(npx / ti / 1e3, 1),
+                       "forward_hbm_frac": round(BYTES_PER_PX * npx / tf / 1e3 / HBM_PEAK_GBS, 4),
+                       "inverse_hbm_frac": round(BYTES_PER_PX * npx / ti / 1e3 / HBM_PEAK_GBS, 4)})
+        w, h = (w + 1) // 2, (h + 1) // 2
+        cur = dst[:h, :w]
+    st, nbytes = dwt2.dwt2_workspace_bytes(wav, lev, W, H)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    tf = _median_us(torch, lambda i: dwt2.forward(x, wav, lev, out=y, workspace=ws), reps)
+    ti = _median_us(torch, lambda i: dwt2.inverse(y, wav, lev, out=z, workspace=ws), reps)
+    total_px = sum(l["width"] * l["height"] for l in levels)
+    return {"workload": f"{name} ({W}x{H}, {wav}, {lev} levels, fused kernel)", "levels": levels,
+            "five_level_forward_us": round(tf, 1), "five_level_inverse_us": round(ti, 1),
+            "five_level_forward_Gpixel_s": round(total_px / tf / 1e3, 1),
+            "five_level_inverse_Gpixel_s": round(total_px / ti / 1e3, 1)}
 
 
 def copy_bandwidth(torch, dev):
