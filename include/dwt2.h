@@ -29,7 +29,8 @@
  *   floor(H/2) x ceil(W/2) block, HH the bottom-right.  Multi-level output is
  *   recursive in the LL block.
  * - Every level's input must be at least 2 x 2: width_k = ceil(W / 2^(k-1))
- *   and height_k >= 2 for k = 1..levels, else DWT2_E_SIZE.
+ *   and height_k >= 2 for k = 1..levels, and width * height <= 2^38, else
+ *   DWT2_E_SIZE.
  * - Ownership: the caller owns src, dst and workspace.  The library never
  *   allocates memory and never synchronises: work is enqueued on `stream`
  *   (0 = the null stream) and completes asynchronously; faults surface at
@@ -49,7 +50,7 @@
 extern "C" {
 #endif
 
-#define DWT2_VERSION 1
+#define DWT2_VERSION 2
 
 /* Status codes. */
 #define DWT2_OK 0
@@ -149,6 +150,55 @@ int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int height,
                  const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
                  dwt2_ext ext, const dwt2_options *opt, void *workspace,
                  size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Batched transforms
+ * ------------------
+ * Many independent images, each with its own wavelet, level count and size,
+ * in one call.  The paper transforms one image at a time; levels of one image
+ * depend on each other through LL (Sec. 1), images do not.  The library
+ * launches one kernel per level index k, covering the tiles of every image
+ * that has a level k, plus a few small kernels that copy the call's image
+ * table into the workspace (their arguments carry the data, so the call may
+ * be captured in a HIP graph; the caller's dwt2_image array may be reused as
+ * soon as the call returns).  Each image gets exactly the coefficients
+ * (resp. samples) that the single-image call with the same arguments gives.
+ *
+ * Scheme: AUTO or MONOLITHIC_STAR (others DWT2_E_UNSUPPORTED); norm and
+ * arithmetic as for single images, shared by the whole batch.
+ * Errors: every image is checked as by dwt2_forward (its status is returned
+ * for the first failing image); count < 0 or count > DWT2_BATCH_MAX, a null
+ * array with count > 0, or a total of more than 2^31 - 8 tiles in one level
+ * -> DWT2_E_ARG; any overlap between one image's dst and another image's src
+ * or dst, or between the workspace and any image -> DWT2_E_ALIAS (ranges are
+ * the bytes from an image's first to its last element).  count == 0 enqueues
+ * nothing.  Calls that share a workspace race unless ordered on one stream.
+ */
+#define DWT2_BATCH_MAX 65536
+
+typedef struct dwt2_image {
+    int wavelet;         /* dwt2_wavelet */
+    int levels;          /* >= 1, every level's input >= 2 x 2 */
+    int width, height;   /* level-0 size (forward input, inverse output) */
+    const float *src;    /* forward: image; inverse: Mallat coefficients */
+    ptrdiff_t src_pitch; /* elements */
+    float *dst;          /* forward: Mallat coefficients; inverse: image */
+    ptrdiff_t dst_pitch; /* elements */
+} dwt2_image;
+
+/* Bytes of device workspace a batched call over these images needs (0 when count == 0). */
+int dwt2_batch_workspace_bytes(const dwt2_image *images, int count, const dwt2_options *opt,
+                               size_t *bytes);
+
+/* Forward transform of `count` images; workspace aligned to 256 bytes. */
+int dwt2_forward_batch(const dwt2_image *images, int count, dwt2_ext ext,
+                       const dwt2_options *opt, void *workspace, size_t workspace_bytes,
+                       hipStream_t stream);
+
+/* Inverse transform of `count` images (src = coefficients, dst = images). */
+int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext ext,
+                       const dwt2_options *opt, void *workspace, size_t workspace_bytes,
+                       hipStream_t stream);
 
 /* Static text for a status code ("unknown status" for others). */
 const char *dwt2_status_string(int status);

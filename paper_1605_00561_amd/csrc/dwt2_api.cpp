@@ -4,8 +4,13 @@
 // the caller's stream.
 #include "../../include/dwt2.h"
 
+#include <limits.h>
 #include <math.h>
 #include <stdint.h>
+
+#include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "dwt2_internal.h"
 
@@ -16,6 +21,8 @@ namespace {
 thread_local int g_last_hip_error = 0;
 
 constexpr int kMaxLevels = 31;
+// 2^38 pixels (1 TiB of FP32) bounds every grid well inside int range.
+constexpr long long kMaxPixels = 1LL << 38;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -56,6 +63,7 @@ int geometry(int levels, int width, int height, int *ws, int *hs)
 {
     if (levels < 1 || width < 1 || height < 1) return DWT2_E_ARG;
     if (levels > kMaxLevels) return DWT2_E_SIZE;
+    if ((long long)width * height > kMaxPixels) return DWT2_E_SIZE;
     int w = width, h = height;
     for (int k = 0; k < levels; k++) {
         if (w < 2 || h < 2) return DWT2_E_SIZE;
@@ -298,4 +306,188 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
         ll_pitch = a.out_pitch;
     }
     return DWT2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched calls.  Workspace: [image records | tile-start table | each image's
+// LL ping-pong, laid out as for the single-image call], each part 256-aligned.
+
+namespace {
+
+struct Interval {
+    uintptr_t lo, hi;
+    bool writes;
+};
+
+// True when some written range overlaps any other range.  Sorting by start,
+// an overlap of a pair always shows against the running maximum end of the
+// earlier ranges of the relevant kind.
+bool any_write_overlap(std::vector<Interval> &v)
+{
+    std::sort(v.begin(), v.end(), [](const Interval &a, const Interval &b) { return a.lo < b.lo; });
+    uintptr_t end_any = 0, end_w = 0;
+    for (const Interval &r : v) {
+        if (r.writes ? r.lo < end_any : r.lo < end_w) return true;
+        end_any = std::max(end_any, r.hi);
+        if (r.writes) end_w = std::max(end_w, r.hi);
+    }
+    return false;
+}
+
+struct BatchPlan {
+    Config cfg;
+    int lmax = 0;
+    size_t rec_off = 0, tab_off = 0, total = 0;
+    std::vector<dwt2::BatchImage> rec;  // buffers as offsets until bound to a workspace
+    std::vector<size_t> buf_off[2];
+    std::vector<int> start;             // lmax x (count + 1)
+    std::vector<std::pair<size_t, size_t>> spans;  // (src bytes, dst bytes)
+};
+
+int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_options *opt,
+               BatchPlan *p)
+{
+    if (count < 0 || count > DWT2_BATCH_MAX || (count > 0 && !images)) return DWT2_E_ARG;
+    int st = parse(DWT2_CDF53, ext, opt, &p->cfg);
+    if (st != DWT2_OK) return st;
+    if (p->cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR) return DWT2_E_UNSUPPORTED;
+    p->rec.resize(count);
+    p->buf_off[0].resize(count);
+    p->buf_off[1].resize(count);
+    p->spans.resize(count);
+    size_t img_bytes = 0;
+    for (int i = 0; i < count; i++) {
+        const dwt2_image &im = images[i];
+        Config c;
+        st = parse((dwt2_wavelet)im.wavelet, ext, opt, &c);
+        if (st != DWT2_OK) return st;
+        int ws[kMaxLevels], hs[kMaxLevels];
+        st = geometry(im.levels, im.width, im.height, ws, hs);
+        if (st != DWT2_OK) return st;
+        if (!im.src || !im.dst) return DWT2_E_ARG;
+        if (im.src_pitch < im.width || im.dst_pitch < im.width) return DWT2_E_ARG;
+        if (((uintptr_t)im.src & 3) || ((uintptr_t)im.dst & 3)) return DWT2_E_ARG;
+        const Layout L = layout(DWT2_SCHEME_MONOLITHIC_STAR, im.levels, ws, hs);
+        p->buf_off[0][i] = img_bytes + L.a_off;
+        p->buf_off[1][i] = img_bytes + L.b_off;
+        img_bytes += L.total;
+        p->spans[i] = {span_bytes(im.src_pitch, im.width, im.height),
+                       span_bytes(im.dst_pitch, im.width, im.height)};
+        dwt2::BatchImage &r = p->rec[i];
+        r.src = im.src;
+        r.dst = im.dst;
+        r.buf[0] = r.buf[1] = nullptr;
+        r.src_pitch = im.src_pitch;
+        r.dst_pitch = im.dst_pitch;
+        r.W = im.width;
+        r.H = im.height;
+        r.wavelet = im.wavelet;
+        r.levels = im.levels;
+        p->lmax = std::max(p->lmax, im.levels);
+    }
+    // Tile starts per level; every level's total must index with an int.
+    p->start.assign((size_t)p->lmax * (count + 1), 0);
+    for (int k = 0; k < p->lmax; k++) {
+        int *s = &p->start[(size_t)k * (count + 1)];
+        long long acc = 0;
+        for (int i = 0; i < count; i++) {
+            s[i] = (int)acc;
+            const dwt2::BatchImage &r = p->rec[i];
+            if (r.levels > k) {
+                const int w = (int)(((long long)r.W + (1LL << k) - 1) >> k);
+                const int h = (int)(((long long)r.H + (1LL << k) - 1) >> k);
+                acc += dwt2::fused_tile_count(r.wavelet, w, h);
+            }
+            if (acc > INT_MAX - 8) return DWT2_E_ARG;
+        }
+        s[count] = (int)acc;
+    }
+    p->rec_off = 0;
+    p->tab_off = align_up(sizeof(dwt2::BatchImage) * (size_t)count);
+    const size_t img_base = p->tab_off + align_up(sizeof(int) * p->start.size());
+    for (int i = 0; i < count; i++) {
+        p->buf_off[0][i] += img_base;
+        p->buf_off[1][i] += img_base;
+    }
+    p->total = img_base + img_bytes;
+    return DWT2_OK;
+}
+
+int run_batch(bool inverse, const dwt2_image *images, int count, dwt2_ext ext,
+              const dwt2_options *opt, void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    BatchPlan p;
+    int st = plan_batch(images, count, ext, opt, &p);
+    if (st != DWT2_OK) return st;
+    if (count == 0) return DWT2_OK;
+    if (!workspace || workspace_bytes < p.total) return DWT2_E_WORKSPACE;
+    if ((uintptr_t)workspace & (kAlign - 1)) return DWT2_E_ARG;
+    std::vector<Interval> iv;
+    iv.reserve(2 * (size_t)count + 1);
+    const uintptr_t w0 = (uintptr_t)workspace;
+    iv.push_back({w0, w0 + p.total, true});
+    for (int i = 0; i < count; i++) {
+        const uintptr_t s0 = (uintptr_t)images[i].src, d0 = (uintptr_t)images[i].dst;
+        iv.push_back({s0, s0 + p.spans[i].first, false});
+        iv.push_back({d0, d0 + p.spans[i].second, true});
+    }
+    if (any_write_overlap(iv)) return DWT2_E_ALIAS;
+
+    char *wsb = (char *)workspace;
+    for (int i = 0; i < count; i++) {
+        p.rec[i].buf[0] = (float *)(wsb + p.buf_off[0][i]);
+        p.rec[i].buf[1] = (float *)(wsb + p.buf_off[1][i]);
+    }
+    hipError_t e = dwt2::launch_upload(wsb + p.rec_off, p.rec.data(),
+                                       sizeof(dwt2::BatchImage) * (size_t)count, stream);
+    if (e == hipSuccess)
+        e = dwt2::launch_upload(wsb + p.tab_off, p.start.data(), sizeof(int) * p.start.size(), stream);
+    if (e != hipSuccess) return hip_status(e);
+
+    dwt2::BatchLevel b;
+    b.imgs = (const dwt2::BatchImage *)(wsb + p.rec_off);
+    b.count = count;
+    b.ll_gain = p.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
+    const int norm = p.cfg.norm;
+    b.s[0] = inverse ? inverse_scale(DWT2_CDF53, norm) : level_scale(DWT2_CDF53, norm);
+    b.s[1] = inverse ? inverse_scale(DWT2_CDF97, norm) : level_scale(DWT2_CDF97, norm);
+    const bool fp64 = p.cfg.arithmetic == DWT2_ARITH_FP64;
+    for (int j = 0; j < p.lmax; j++) {
+        const int k = inverse ? p.lmax - 1 - j : j;
+        b.level = k;
+        b.start = (const int *)(wsb + p.tab_off) + (size_t)k * (count + 1);
+        b.ntiles = p.start[(size_t)k * (count + 1) + count];
+        b.quantum = norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
+        e = inverse ? dwt2::launch_batch_inverse(fp64, b, stream)
+                    : dwt2::launch_batch_forward(fp64, b, stream);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    return DWT2_OK;
+}
+
+}  // namespace
+
+DWT2_EXPORT int dwt2_batch_workspace_bytes(const dwt2_image *images, int count,
+                                           const dwt2_options *opt, size_t *bytes)
+{
+    if (!bytes) return DWT2_E_ARG;
+    BatchPlan p;
+    const int st = plan_batch(images, count, DWT2_EXT_WHOLE_SYMMETRIC, opt, &p);
+    if (st != DWT2_OK) return st;
+    *bytes = p.total;
+    return DWT2_OK;
+}
+
+DWT2_EXPORT int dwt2_forward_batch(const dwt2_image *images, int count, dwt2_ext ext,
+                                   const dwt2_options *opt, void *workspace, size_t workspace_bytes,
+                                   hipStream_t stream)
+{
+    return run_batch(false, images, count, ext, opt, workspace, workspace_bytes, stream);
+}
+
+DWT2_EXPORT int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext ext,
+                                   const dwt2_options *opt, void *workspace, size_t workspace_bytes,
+                                   hipStream_t stream)
+{
+    return run_batch(true, images, count, ext, opt, workspace, workspace_bytes, stream);
 }

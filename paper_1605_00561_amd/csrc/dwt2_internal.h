@@ -114,6 +114,44 @@ hipError_t launch_tile_inverse(int wavelet, int scheme, const InvArgs &a, hipStr
 hipError_t launch_fused_forward(int wavelet, bool fp64, const FwdArgs &a, hipStream_t s);
 hipError_t launch_fused_inverse(int wavelet, bool fp64, const InvArgs &a, hipStream_t s);
 
+// Batched fused launches.  One record per image, in device memory; a level
+// launch covers the tiles of every image that has that level.  The buffer
+// roles per level are those of the single-image level loop:
+//   forward level k reads `src` (k = 0) or buf[(k-1)&1] (pitch = level width)
+//   and writes LL to `dst` (last level) or buf[k&1] (pitch = LL width);
+//   inverse level k reads LL from `src` (last level) or buf[k&1] and writes
+//   `dst` (k = 0) or buf[(k-1)&1]; details are always in the Mallat array.
+struct BatchImage {
+    const float *src;  // forward: image; inverse: coefficients
+    float *dst;        // forward: coefficients; inverse: image
+    float *buf[2];     // LL ping-pong (unused when levels == 1)
+    ptrdiff_t src_pitch, dst_pitch;
+    int W, H;          // level-0 size
+    int wavelet, levels;
+};
+static_assert(sizeof(BatchImage) == 64, "BatchImage is a 64-byte record");
+
+// One batched level.  `start` has count + 1 entries: the tiles of image i are
+// [start[i], start[i+1]) (empty when the image has no level k); start[count]
+// is the total.
+struct BatchLevel {
+    const BatchImage *imgs;
+    const int *start;
+    int count, ntiles, level;
+    Scale s[2];     // per wavelet: forward scales, or reciprocals for the inverse
+    float ll_gain;
+    float quantum;
+};
+
+// Tiles of the fused kernel for one W x H level (0 when a side is below 2).
+long long fused_tile_count(int wavelet, int W, int H);
+hipError_t launch_batch_forward(bool fp64, const BatchLevel &b, hipStream_t s);
+hipError_t launch_batch_inverse(bool fp64, const BatchLevel &b, hipStream_t s);
+// Copy `bytes` (a multiple of 4) from host memory to device memory `dst` with
+// kernels whose arguments carry the data: stream-ordered and capturable, and
+// the host buffer may be reused as soon as the call returns.
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);
+
 // Row-column: the intermediate `tmp` is W x H with pitch tmp_pitch.
 hipError_t launch_rowcol_forward(int wavelet, const FwdArgs &a, float *tmp, ptrdiff_t tmp_pitch,
                                  hipStream_t s);

@@ -28,6 +28,8 @@
 // quadruple row and adds c * ll_gain back to LL (exact by linearity).
 // Tiles are numbered so that each XCD (work-group id mod 8) takes a
 // contiguous row-major run, so neighbouring tiles share their halo in L2.
+#include <string.h>
+
 #include "dwt2_internal.h"
 
 namespace dwt2 {
@@ -471,6 +473,135 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, 
         inv_body<WAV, T, false>(a, sm, tc, tr, w, lane);
 }
 
+// Batched levels.  A work-group finds its image by a search over the tile
+// starts that costs one coalesced load per 64-fold narrowing (two for up to
+// 4096 images), then runs the same tile body as the single-image kernel, so
+// every image gets the bits the single-image call gives it.
+__device__ __forceinline__ int find_image(const int *__restrict__ start, int count, int t)
+{
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = count;  // start[lo] <= t, and start[hi] > t unless hi == count
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) / 64;
+        const int idx = lo + lane * step;
+        const bool le = idx < hi && start[idx] <= t;  // true on a prefix of the lanes
+        const int m = __popcll(__ballot(le)) - 1;     // lane 0 is always true
+        lo = __builtin_amdgcn_readfirstlane(lo + m * step);
+        hi = min(lo + step, hi);
+    }
+    return lo;
+}
+
+// Level-k geometry of image `im`: size, and the pointers of the level loop.
+__device__ __forceinline__ int level_size(int n, int k)
+{
+    return (int)(((long long)n + (1LL << k) - 1) >> k);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_batch_forward(BatchLevel b)
+{
+    __shared__ Seams<T> sm;
+    const int t = xcd_tile(b.ntiles);
+    if (t < 0) return;
+    const int i = find_image(b.start, b.count, t);
+    const BatchImage &im = b.imgs[i];
+    const int k = b.level, last = im.levels - 1;
+    const int W = level_size(im.W, k), H = level_size(im.H, k);
+    FwdArgs a;
+    a.in = k == 0 ? im.src : im.buf[(k - 1) & 1];
+    a.in_pitch = k == 0 ? im.src_pitch : (ptrdiff_t)W;
+    a.ll = k == last ? im.dst : im.buf[k & 1];
+    a.ll_pitch = k == last ? im.dst_pitch : (ptrdiff_t)((W + 1) / 2);
+    a.det = im.dst;
+    a.det_pitch = im.dst_pitch;
+    a.W = W;
+    a.H = H;
+    a.s = b.s[im.wavelet == CDF97];
+    a.ll_gain = b.ll_gain;
+    a.quantum = b.quantum;
+    const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
+    const int local = t - b.start[i];
+    const bool aligned = (((uintptr_t)a.in | (uintptr_t)(a.in_pitch * 4)) & 7) == 0;
+    if (im.wavelet == CDF97) {
+        constexpr int HQ = Lift<CDF97>::K;
+        const int ntx = ((W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
+        const int tc = local % ntx, tr = local / ntx;
+        const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+        if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
+            fwd_body<CDF97, T, true>(a, sm, tc, tr, w, lane);
+        else
+            fwd_body<CDF97, T, false>(a, sm, tc, tr, w, lane);
+    } else {
+        constexpr int HQ = Lift<CDF53>::K;
+        const int ntx = ((W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
+        const int tc = local % ntx, tr = local / ntx;
+        const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+        if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
+            fwd_body<CDF53, T, true>(a, sm, tc, tr, w, lane);
+        else
+            fwd_body<CDF53, T, false>(a, sm, tc, tr, w, lane);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_batch_inverse(BatchLevel b)
+{
+    __shared__ Seams<T> sm;
+    const int t = xcd_tile(b.ntiles);
+    if (t < 0) return;
+    const int i = find_image(b.start, b.count, t);
+    const BatchImage &im = b.imgs[i];
+    const int k = b.level, last = im.levels - 1;
+    const int W = level_size(im.W, k), H = level_size(im.H, k);
+    InvArgs a;
+    a.ll = k == last ? im.src : im.buf[k & 1];
+    a.ll_pitch = k == last ? im.src_pitch : (ptrdiff_t)((W + 1) / 2);
+    a.det = im.src;
+    a.det_pitch = im.src_pitch;
+    a.out = k == 0 ? im.dst : im.buf[(k - 1) & 1];
+    a.out_pitch = k == 0 ? im.dst_pitch : (ptrdiff_t)W;
+    a.W = W;
+    a.H = H;
+    a.inv_s = b.s[im.wavelet == CDF97];
+    a.ll_gain = b.ll_gain;
+    a.quantum = b.quantum;
+    const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
+    const int local = t - b.start[i];
+    const bool aligned = (((uintptr_t)a.out | (uintptr_t)(a.out_pitch * 4)) & 7) == 0;
+    if (im.wavelet == CDF97) {
+        constexpr int HQ = Lift<CDF97>::K;
+        const int ntx = ((W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
+        const int tc = local % ntx, tr = local / ntx;
+        const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+        if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
+            inv_body<CDF97, T, true>(a, sm, tc, tr, w, lane);
+        else
+            inv_body<CDF97, T, false>(a, sm, tc, tr, w, lane);
+    } else {
+        constexpr int HQ = Lift<CDF53>::K;
+        const int ntx = ((W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
+        const int tc = local % ntx, tr = local / ntx;
+        const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+        if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
+            inv_body<CDF53, T, true>(a, sm, tc, tr, w, lane);
+        else
+            inv_body<CDF53, T, false>(a, sm, tc, tr, w, lane);
+    }
+}
+
+// Host-to-device copy through kernel arguments (at most kUploadWords words
+// per launch; kernel arguments are captured by value in a graph).
+constexpr int kUploadWords = 768;
+struct UploadChunk {
+    uint32_t w[kUploadWords];
+};
+
+__global__ __launch_bounds__(256) void k_upload(uint32_t *dst, int n, UploadChunk c)
+{
+    for (int j = threadIdx.x; j < n; j += 256) dst[j] = c.w[j];
+}
+
 struct Grid {
     int ntx, ntiles, blocks;
 };
@@ -514,6 +645,42 @@ hipError_t launch_fused_inverse(int wavelet, bool fp64, const InvArgs &a, hipStr
         return fp64 ? launch(k_fused_inverse<CDF97, double>, grid, block, s, a, g.ntx, g.ntiles)
                     : launch(k_fused_inverse<CDF97, float>, grid, block, s, a, g.ntx, g.ntiles);
     return hipErrorInvalidValue;
+}
+
+long long fused_tile_count(int wavelet, int W, int H)
+{
+    if (W < 2 || H < 2) return 0;
+    const int HQ = wavelet == CDF97 ? 2 : 1;
+    const long long QW = (W + 1LL) / 2, QH = (H + 1LL) / 2;
+    const int ix = TX - 2 * HQ, iy = TY - 2 * HQ;
+    return ((QW + ix - 1) / ix) * ((QH + iy - 1) / iy);
+}
+
+hipError_t launch_batch_forward(bool fp64, const BatchLevel &b, hipStream_t s)
+{
+    const dim3 grid((b.ntiles + 7) / 8 * 8), block(NTHREADS);
+    return fp64 ? launch(k_batch_forward<double>, grid, block, s, b)
+                : launch(k_batch_forward<float>, grid, block, s, b);
+}
+
+hipError_t launch_batch_inverse(bool fp64, const BatchLevel &b, hipStream_t s)
+{
+    const dim3 grid((b.ntiles + 7) / 8 * 8), block(NTHREADS);
+    return fp64 ? launch(k_batch_inverse<double>, grid, block, s, b)
+                : launch(k_batch_inverse<float>, grid, block, s, b);
+}
+
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const size_t words = bytes / 4;
+    for (size_t off = 0; off < words; off += kUploadWords) {
+        const int n = (int)(words - off < (size_t)kUploadWords ? words - off : kUploadWords);
+        UploadChunk c{};
+        memcpy(c.w, (const uint32_t *)src + off, sizeof(uint32_t) * n);
+        const hipError_t e = launch(k_upload, dim3(1), dim3(256), s, (uint32_t *)dst + off, n, c);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace dwt2

@@ -31,7 +31,9 @@ SCHEMES = {"auto": SCHEME_AUTO, "monolithic*": SCHEME_MONOLITHIC_STAR,
 SCHEMES.update({v: v for v in list(SCHEMES.values())})
 
 EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_string",
-           "dwt2_last_hip_error", "dwt2_version"]
+           "dwt2_last_hip_error", "dwt2_version", "dwt2_batch_workspace_bytes",
+           "dwt2_forward_batch", "dwt2_inverse_batch"]
+BATCH_MAX = 65536
 
 
 ARITH_AUTO, ARITH_FP32, ARITH_FP64 = 0, 1, 2
@@ -42,6 +44,13 @@ ARITHS = {"auto": ARITH_AUTO, "fp32": ARITH_FP32, "fp64": ARITH_FP64,
 class Options(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_int), ("scheme", ctypes.c_int), ("arithmetic", ctypes.c_int),
                 ("reserved", ctypes.c_int * 5)]
+
+
+class Image(ctypes.Structure):
+    """struct dwt2_image: one image of a batched call."""
+    _fields_ = [("wavelet", ctypes.c_int), ("levels", ctypes.c_int), ("width", ctypes.c_int),
+                ("height", ctypes.c_int), ("src", ctypes.c_void_p), ("src_pitch", ctypes.c_ssize_t),
+                ("dst", ctypes.c_void_p), ("dst_pitch", ctypes.c_ssize_t)]
 
 
 class Dwt2Error(RuntimeError):
@@ -72,6 +81,12 @@ def _load() -> ctypes.CDLL:
     L.dwt2_forward.restype = L.dwt2_inverse.restype = i
     L.dwt2_workspace_bytes.argtypes = [i, i, i, i, ctypes.POINTER(Options), ctypes.POINTER(sz)]
     L.dwt2_workspace_bytes.restype = i
+    ip = ctypes.POINTER(Image)
+    L.dwt2_batch_workspace_bytes.argtypes = [ip, i, ctypes.POINTER(Options), ctypes.POINTER(sz)]
+    L.dwt2_forward_batch.argtypes = [ip, i, i, ctypes.POINTER(Options), vp, sz, vp]
+    L.dwt2_inverse_batch.argtypes = L.dwt2_forward_batch.argtypes
+    L.dwt2_batch_workspace_bytes.restype = i
+    L.dwt2_forward_batch.restype = L.dwt2_inverse_batch.restype = i
     L.dwt2_status_string.argtypes = [i]
     L.dwt2_status_string.restype = ctypes.c_char_p
     L.dwt2_last_hip_error.argtypes = []
@@ -129,6 +144,38 @@ def dwt2_inverse(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch,
     return _lib.dwt2_inverse(WAVELETS[wavelet], levels, width, height, src, src_pitch, dst,
                              dst_pitch, ext, ctypes.byref(opt) if opt is not None else None,
                              workspace, workspace_bytes, stream)
+
+
+def make_images(entries) -> ctypes.Array:
+    """A dwt2_image array from (wavelet, levels, width, height, src, src_pitch,
+    dst, dst_pitch) tuples."""
+    arr = (Image * max(len(entries), 1))()
+    for k, (wav, lev, w, h, src, sp, dst, dp) in enumerate(entries):
+        arr[k] = Image(WAVELETS[wav], lev, w, h, src, sp, dst, dp)
+    return arr
+
+
+def dwt2_batch_workspace_bytes(images, count, opt: Options | None = None):
+    """(status, bytes)."""
+    n = ctypes.c_size_t(0)
+    st = _lib.dwt2_batch_workspace_bytes(images, count,
+                                         ctypes.byref(opt) if opt is not None else None,
+                                         ctypes.byref(n))
+    return st, n.value
+
+
+def dwt2_forward_batch(images, count, ext, opt: Options | None, workspace, workspace_bytes,
+                       stream) -> int:
+    return _lib.dwt2_forward_batch(images, count, ext,
+                                   ctypes.byref(opt) if opt is not None else None, workspace,
+                                   workspace_bytes, stream)
+
+
+def dwt2_inverse_batch(images, count, ext, opt: Options | None, workspace, workspace_bytes,
+                       stream) -> int:
+    return _lib.dwt2_inverse_batch(images, count, ext,
+                                   ctypes.byref(opt) if opt is not None else None, workspace,
+                                   workspace_bytes, stream)
 
 
 # --- torch conveniences -------------------------------------------------------
@@ -196,3 +243,66 @@ def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=
     if st != OK:
         raise Dwt2Error(st, "dwt2_inverse")
     return out
+
+
+class Batch:
+    """A fixed set of images for repeated batched calls (the image table is
+    built once on the host; each call still copies it to the device, as the
+    C entry point does).  ``inputs`` and ``outputs`` are lists of (H, W)
+    float32 device tensors; ``wavelets`` and ``levels`` have one entry per
+    image."""
+
+    def __init__(self, inputs, outputs, wavelets, levels, norm="unit_dc", arithmetic="auto",
+                 inverse=False, workspace=None):
+        import torch
+        if not (len(inputs) == len(outputs) == len(wavelets) == len(levels)):
+            raise ValueError("inputs, outputs, wavelets and levels differ in length")
+        entries = []
+        for x, y, wav, lev in zip(inputs, outputs, wavelets, levels):
+            _check_image(x)
+            _check_image(y)
+            if x.shape != y.shape:
+                raise ValueError("input and output shapes differ")
+            h, w = x.shape
+            entries.append((wav, int(lev), w, h, x.data_ptr(), x.stride(0), y.data_ptr(),
+                            y.stride(0)))
+        self.inputs, self.outputs = list(inputs), list(outputs)
+        self.count = len(entries)
+        self.images = make_images(entries)
+        self.opt = make_options(norm, "auto", arithmetic)
+        self.inverse = inverse
+        st, nbytes = dwt2_batch_workspace_bytes(self.images, self.count, self.opt)
+        if st != OK:
+            raise Dwt2Error(st, "dwt2_batch_workspace_bytes")
+        device = inputs[0].device if inputs else torch.device("cuda")
+        if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+            workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        self.workspace = workspace
+        self.workspace_bytes = workspace.numel() * workspace.element_size()
+
+    def __call__(self, stream=None):
+        fn = dwt2_inverse_batch if self.inverse else dwt2_forward_batch
+        st = fn(self.images, self.count, EXT_WHOLE_SYMMETRIC, self.opt,
+                self.workspace.data_ptr(), self.workspace_bytes, _stream_handle(stream))
+        if st != OK:
+            raise Dwt2Error(st, fn.__name__)
+        return self.outputs
+
+
+def forward_batch(images, wavelets, levels, norm="unit_dc", arithmetic="auto", outs=None,
+                  stream=None):
+    """Forward DWT of a list of (H, W) float32 device tensors in one batched
+    call; returns their Mallat layouts."""
+    import torch
+    if outs is None:
+        outs = [torch.empty_like(x) for x in images]
+    return Batch(images, outs, wavelets, levels, norm, arithmetic)(stream)
+
+
+def inverse_batch(coefs, wavelets, levels, norm="unit_dc", arithmetic="auto", outs=None,
+                  stream=None):
+    """Inverse DWT of a list of Mallat-layout device tensors in one batched call."""
+    import torch
+    if outs is None:
+        outs = [torch.empty_like(x) for x in coefs]
+    return Batch(coefs, outs, wavelets, levels, norm, arithmetic, inverse=True)(stream)

@@ -16,6 +16,8 @@ unspecified, so these synthetic images stand in for them):
 * ``batch_specs``     512 (w, h, wavelet, levels) tuples, w and h uniform over
                       the even integers in [256, 4096], wavelet 5/3 or 9/7 with
                       probability 1/2, levels uniform in {3, 4, 5, 6}.
+* ``batch_image``     the pixels of image i of a batch: integers uniform in
+                      [0, 255], drawn from the seed sequence (seed, i).
 """
 from __future__ import annotations
 
@@ -95,3 +97,10 @@ def batch_specs(n: int = 512, seed: int = 3):
         lev = int(rng.integers(3, 7))
         out.append((w, h, wav, lev))
     return out
+
+
+def batch_image(i: int, width: int, height: int, seed: int = 3) -> np.ndarray:
+    """Pixels of image i of a batch (uint8 values, returned as uint8 to keep
+    host memory small; cast to FP32 on the device)."""
+    rng = np.random.default_rng([seed, i])
+    return rng.integers(0, 256, size=(height, width), dtype=np.uint8)

@@ -105,6 +105,10 @@ def test_size_errors():
     assert _fwd(height=1) == dwt2.E_SIZE
     assert _fwd(levels=5) == dwt2.E_SIZE        # 16 -> 8 -> 4 -> 2 -> 1
     assert _fwd(levels=40) == dwt2.E_SIZE
+    big = 2 ** 19  # at most 2^38 pixels
+    assert _fwd(width=big, height=big + 1, src_pitch=big, dst_pitch=big) == dwt2.E_SIZE
+    assert dwt2.dwt2_workspace_bytes("cdf53", 2, big, big, None) == \
+        (dwt2.OK, _al(4 * (big // 2) ** 2))
 
 
 def test_unsupported():
