@@ -15,6 +15,9 @@ line:
                register-blocked Monolithic*, and in the LDS tile harness
                Monolithic* (2 barriers per pair), separable Sweldens (4) and
                Iwahashi (3), plus the row-column separable two-pass kernels
+  pyramid      per-level and five-level times of the 16384^2 9/7 pyramid
+  batch        512 uneven images: batched call, HIP-graph replay, and one
+               call per image (images/s, p99, fraction of 8 TB/s)
   cpu_baseline the FP64 CPU oracle on the host cores, forward + inverse of the
                same image
 """
@@ -48,6 +51,8 @@ def parse():
     ap.add_argument("--no-schemes", action="store_true")
     ap.add_argument("--no-pyramid", action="store_true",
                     help="skip the per-level table of the 16384^2 five-level workload")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 512-image batched workload")
     ap.add_argument("--no-copy", action="store_true",
                     help="skip the device-to-device copy (the bandwidth and counter reference)")
     return ap.parse_args()
@@ -154,6 +159,10 @@ def main():
         del xs, ys, zs
         torch.cuda.empty_cache()
         out["pyramid"] = pyramid_table(dwt2, torch, workloads, args.scheme_reps)
+    if not args.no_batch:
+        torch.cuda.empty_cache()
+        out["batch"] = batch_table(dwt2, torch, workloads, args.scheme_reps)
+        torch.cuda.empty_cache()
     if not args.no_copy:
         out["copy_GBs"] = copy_bandwidth(torch, dev)
 
@@ -252,6 +261,102 @@ def pyramid_table(dwt2, torch, workloads, reps):
             "five_level_forward_us": round(tf, 1), "five_level_inverse_us": round(ti, 1),
             "five_level_forward_Gpixel_s": round(total_px / tf / 1e3, 1),
             "five_level_inverse_Gpixel_s": round(total_px / ti / 1e3, 1)}
+
+
+def _times_us(torch, fn, reps):
+    stream = torch.cuda.current_stream()
+    fn()
+    ev = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    return sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+
+
+def batch_table(dwt2, torch, workloads, reps):
+    """512 uneven images (even sizes 256..4096, 5/3 or 9/7, 3..6 levels):
+    one batched call (one fused launch per level index over all images, plus
+    the image-table copy kernels), the same call replayed from a HIP graph, and
+    one single-image call per image (one launch per image per level)."""
+    dev = torch.device("cuda:0")
+    specs = workloads.batch_specs()
+    xs = [torch.from_numpy(workloads.batch_image(i, w, h)).to(dev).float()
+          for i, (w, h, _, _) in enumerate(specs)]
+    ys = [torch.empty_like(x) for x in xs]
+    zs = [torch.empty_like(x) for x in xs]
+    wavs, levs = [s[2] for s in specs], [s[3] for s in specs]
+    fwd = dwt2.Batch(xs, ys, wavs, levs)
+    inv = dwt2.Batch(ys, zs, wavs, levs, inverse=True)
+    px0 = sum(w * h for (w, h, _, _) in specs)
+    px_all = 0
+    for (w, h, _, lev) in specs:
+        for _ in range(lev):
+            px_all += w * h
+            w, h = (w + 1) // 2, (h + 1) // 2
+    n = len(specs)
+
+    def row(times):
+        med = statistics.median(times)
+        return {"median_us": round(med, 1), "p99_us": round(times[min(len(times) - 1,
+                                                                       int(0.99 * len(times)))], 1),
+                "images_per_s": round(n / med * 1e6, 1),
+                "Gpixel_s": round(px0 / med / 1e3, 1),
+                "hbm_frac": round(BYTES_PER_PX * px_all / med / 1e3 / HBM_PEAK_GBS, 4)}
+
+    out = {"workload": f"{n} images, even sides uniform in [256, 4096], cdf53/cdf97, "
+                       f"3-6 levels (seed 3)",
+           "level0_pixels": px0, "all_level_pixels": px_all,
+           "algorithmic_bytes": int(BYTES_PER_PX * px_all)}
+    out["batched_forward"] = row(_times_us(torch, fwd, reps))
+    out["batched_inverse"] = row(_times_us(torch, inv, reps))
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fwd()
+        inv()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    gf, gi = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gf):
+        fwd()
+    with torch.cuda.graph(gi):
+        inv()
+    out["graph_forward"] = row(_times_us(torch, gf.replay, reps))
+    out["graph_inverse"] = row(_times_us(torch, gi.replay, reps))
+
+    # one call per image through the C ABI, arguments prepared beforehand
+    stream = torch.cuda.current_stream().cuda_stream
+    calls = []
+    for x, y, z, wav, lev in zip(xs, ys, zs, wavs, levs):
+        h, w = x.shape
+        st, nb = dwt2.dwt2_workspace_bytes(wav, lev, w, h)
+        ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        calls.append((wav, lev, w, h, x, y, z, ws, nb))
+
+    def loop(inverse):
+        f = dwt2.dwt2_inverse if inverse else dwt2.dwt2_forward
+        for (wav, lev, w, h, x, y, z, ws, nb) in calls:
+            a, b = (y, z) if inverse else (x, y)
+            st = f(wav, lev, w, h, a.data_ptr(), w, b.data_ptr(), w, 0, None, ws.data_ptr(), nb,
+                   stream)
+            if st != dwt2.OK:
+                raise dwt2.Dwt2Error(st, "per-image call")
+
+    out["per_image_forward"] = row(_times_us(torch, lambda: loop(False), reps))
+    out["per_image_inverse"] = row(_times_us(torch, lambda: loop(True), reps))
+    lmax = max(levs)
+    out["launches_per_direction"] = {
+        "batched": -(-16 * n // 768) - (-lmax * (n + 1) // 768) + lmax,  # table copies + levels
+        "per_image": sum(levs)}
+    torch.cuda.synchronize()
+    rt = max(float((z - x).abs().max()) for x, z in zip(xs, zs))
+    out["round_trip_max_abs"] = rt
+    return out
 
 
 def copy_bandwidth(torch, dev):
