@@ -60,6 +60,7 @@ extern "C" {
 #define DWT2_E_WORKSPACE (-4)   /* workspace missing or smaller than dwt2_workspace_bytes() */
 #define DWT2_E_ALIAS (-5)       /* src and dst (or workspace) overlap */
 #define DWT2_E_HIP (-6)         /* a HIP launch failed; see dwt2_last_hip_error() */
+#define DWT2_E_STATE (-7)       /* server stopping, or unknown / already collected ticket */
 
 /* Wavelets (Sec. 5, "Evaluation"). */
 typedef enum dwt2_wavelet {
@@ -199,6 +200,90 @@ int dwt2_forward_batch(const dwt2_image *images, int count, dwt2_ext ext,
 int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext ext,
                        const dwt2_options *opt, void *workspace, size_t workspace_bytes,
                        hipStream_t stream);
+
+/*
+ * Serving loop (continuous batching)
+ * ----------------------------------
+ * A server takes single-image requests from any number of host threads and
+ * runs them through the batched transform on one stream.  A scheduler thread
+ * forms each batch from the requests pending at that moment (first come,
+ * first served, at most max_batch), as long as fewer than max_inflight
+ * batches are enqueued and not finished; so under light load a request is
+ * launched at once, and under heavy load batches grow.  Admission is by
+ * footprint: a batch's workspace (image table + each image's LL buffers)
+ * is carved from the caller's device arena, and a request waits while the
+ * arena is full.  A completion thread retires finished batches (in stream
+ * order) and records each request's latency (submission to observed
+ * completion, host clock).
+ *
+ * Ordering: requests whose buffers overlap (one writes what another reads or
+ * writes) never share a batch, and batches run in submission order on the
+ * stream, so a request may consume an earlier request's output.
+ * Each request gets exactly the result of dwt2_forward / dwt2_inverse with
+ * the server's options.  The arena, and every request's src and dst, are
+ * owned by the caller and must stay valid until the request completes.
+ */
+typedef struct dwt2_server dwt2_server;
+
+typedef struct dwt2_request {
+    int inverse;         /* 0 = forward (src image -> dst coefficients), 1 = inverse */
+    int wavelet;         /* dwt2_wavelet */
+    int levels;
+    int width, height;
+    const float *src;
+    ptrdiff_t src_pitch; /* elements */
+    float *dst;
+    ptrdiff_t dst_pitch; /* elements */
+} dwt2_request;
+
+typedef struct dwt2_server_config {
+    int max_batch;    /* requests per batch, 1..DWT2_BATCH_MAX (0 = 256) */
+    int max_inflight; /* batches enqueued and not finished, >= 1 (0 = 2) */
+    int reserved[6];  /* must be zero */
+} dwt2_server_config;
+
+typedef struct dwt2_completion {
+    int status;        /* DWT2_OK or the status of the failed launch */
+    double queue_us;   /* submission -> batch enqueued */
+    double latency_us; /* submission -> completion observed */
+} dwt2_completion;
+
+/*
+ * Start a server.  opt: shared normalisation / arithmetic (scheme AUTO or
+ * MONOLITHIC_STAR); cfg may be NULL.  arena: device memory (256-byte
+ * aligned) for batch workspaces.  Creates threads and HIP events; no device
+ * memory is allocated.  *out receives the handle.
+ */
+int dwt2_server_create(const dwt2_options *opt, const dwt2_server_config *cfg, void *arena,
+                       size_t arena_bytes, hipStream_t stream, dwt2_server **out);
+
+/*
+ * Queue one request; returns at once.  The request is validated as by
+ * dwt2_forward (status returned, nothing queued); a request whose workspace
+ * alone exceeds the arena gives DWT2_E_WORKSPACE, one overlapping the arena
+ * DWT2_E_ALIAS.  *ticket identifies it for dwt2_server_wait.
+ */
+int dwt2_server_submit(dwt2_server *server, const dwt2_request *request,
+                       unsigned long long *ticket);
+
+/*
+ * Block until the request `ticket` has completed; fill *done (may be NULL)
+ * and return its status.  Each ticket can be waited for once.
+ */
+int dwt2_server_wait(dwt2_server *server, unsigned long long ticket, dwt2_completion *done);
+
+/*
+ * Submit requests[i] at arrival_us[i] microseconds after the call starts
+ * (non-decreasing; the calling thread spins until each arrival time), then
+ * wait for all of them and fill done[i].  A load generator for measuring
+ * latency under a given arrival process.  Returns DWT2_OK, or the first
+ * submission error (requests before it are still waited for).
+ */
+int dwt2_server_replay(dwt2_server *server, const dwt2_request *requests,
+                       const double *arrival_us, int count, dwt2_completion *done);
+
+/* Finish every queued request, stop the threads and free the handle. */
+int dwt2_server_destroy(dwt2_server *server);
 
 /* Static text for a status code ("unknown status" for others). */
 const char *dwt2_status_string(int status);

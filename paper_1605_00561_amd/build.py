@@ -24,7 +24,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdwt2.so")
 ARCH = os.environ.get("DWT2_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["dwt2_api.cpp", "tile_kernels.hip", "fused_kernels.hip", "rowcol_kernels.hip"]
+SOURCES = ["dwt2_api.cpp", "dwt2_server.cpp", "tile_kernels.hip", "fused_kernels.hip",
+           "rowcol_kernels.hip"]
 HEADERS = ["dwt2_internal.h"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -62,7 +63,7 @@ def build(force: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, force), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs,
            "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -191,6 +191,7 @@ DWT2_EXPORT const char *dwt2_status_string(int status)
     case DWT2_E_WORKSPACE: return "workspace missing or too small";
     case DWT2_E_ALIAS: return "src, dst or workspace overlap";
     case DWT2_E_HIP: return "HIP launch failed";
+    case DWT2_E_STATE: return "server stopping, or unknown or already collected ticket";
     default: return "unknown status";
     }
 }
@@ -312,6 +313,12 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
 // Batched calls.  Workspace: [image records | tile-start table | each image's
 // LL ping-pong, laid out as for the single-image call], each part 256-aligned.
 
+size_t dwt2::batch_table_bytes(int count, int lmax)
+{
+    return align_up(sizeof(dwt2::BatchImage) * (size_t)count) +
+           align_up(sizeof(int) * (size_t)lmax * (size_t)(count + 1));
+}
+
 namespace {
 
 struct Interval {
@@ -404,7 +411,7 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
     }
     p->rec_off = 0;
     p->tab_off = align_up(sizeof(dwt2::BatchImage) * (size_t)count);
-    const size_t img_base = p->tab_off + align_up(sizeof(int) * p->start.size());
+    const size_t img_base = dwt2::batch_table_bytes(count, p->lmax);
     for (int i = 0; i < count; i++) {
         p->buf_off[0][i] += img_base;
         p->buf_off[1][i] += img_base;

@@ -143,6 +143,10 @@ struct BatchLevel {
     float quantum;
 };
 
+// Bytes of a batched call's workspace before the per-image LL buffers: the
+// image records and the tile-start table, each 256-byte aligned.
+size_t batch_table_bytes(int count, int lmax);
+
 // Tiles of the fused kernel for one W x H level (0 when a side is below 2).
 long long fused_tile_count(int wavelet, int W, int H);
 hipError_t launch_batch_forward(bool fp64, const BatchLevel &b, hipStream_t s);

@@ -15,7 +15,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdwt2.so")
 
-OK, E_ARG, E_SIZE, E_UNSUPPORTED, E_WORKSPACE, E_ALIAS, E_HIP = 0, -1, -2, -3, -4, -5, -6
+OK, E_ARG, E_SIZE, E_UNSUPPORTED, E_WORKSPACE, E_ALIAS, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 CDF53, CDF97 = 0, 1
 EXT_WHOLE_SYMMETRIC = 0
 NORM_UNIT_DC, NORM_PAPER = 0, 1
@@ -32,7 +32,8 @@ SCHEMES.update({v: v for v in list(SCHEMES.values())})
 
 EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_string",
            "dwt2_last_hip_error", "dwt2_version", "dwt2_batch_workspace_bytes",
-           "dwt2_forward_batch", "dwt2_inverse_batch"]
+           "dwt2_forward_batch", "dwt2_inverse_batch", "dwt2_server_create", "dwt2_server_submit",
+           "dwt2_server_wait", "dwt2_server_replay", "dwt2_server_destroy"]
 BATCH_MAX = 65536
 
 
@@ -51,6 +52,24 @@ class Image(ctypes.Structure):
     _fields_ = [("wavelet", ctypes.c_int), ("levels", ctypes.c_int), ("width", ctypes.c_int),
                 ("height", ctypes.c_int), ("src", ctypes.c_void_p), ("src_pitch", ctypes.c_ssize_t),
                 ("dst", ctypes.c_void_p), ("dst_pitch", ctypes.c_ssize_t)]
+
+
+class Request(ctypes.Structure):
+    """struct dwt2_request: one request to a server."""
+    _fields_ = [("inverse", ctypes.c_int), ("wavelet", ctypes.c_int), ("levels", ctypes.c_int),
+                ("width", ctypes.c_int), ("height", ctypes.c_int), ("src", ctypes.c_void_p),
+                ("src_pitch", ctypes.c_ssize_t), ("dst", ctypes.c_void_p),
+                ("dst_pitch", ctypes.c_ssize_t)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int), ("max_inflight", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("queue_us", ctypes.c_double),
+                ("latency_us", ctypes.c_double)]
 
 
 class Dwt2Error(RuntimeError):
@@ -87,6 +106,17 @@ def _load() -> ctypes.CDLL:
     L.dwt2_inverse_batch.argtypes = L.dwt2_forward_batch.argtypes
     L.dwt2_batch_workspace_bytes.restype = i
     L.dwt2_forward_batch.restype = L.dwt2_inverse_batch.restype = i
+    sp = ctypes.c_void_p  # dwt2_server *
+    u64 = ctypes.c_ulonglong
+    L.dwt2_server_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(ServerConfig), vp, sz,
+                                     vp, ctypes.POINTER(sp)]
+    L.dwt2_server_submit.argtypes = [sp, ctypes.POINTER(Request), ctypes.POINTER(u64)]
+    L.dwt2_server_wait.argtypes = [sp, u64, ctypes.POINTER(Completion)]
+    L.dwt2_server_replay.argtypes = [sp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_double),
+                                     i, ctypes.POINTER(Completion)]
+    L.dwt2_server_destroy.argtypes = [sp]
+    for f in ("create", "submit", "wait", "replay", "destroy"):
+        getattr(L, "dwt2_server_" + f).restype = i
     L.dwt2_status_string.argtypes = [i]
     L.dwt2_status_string.restype = ctypes.c_char_p
     L.dwt2_last_hip_error.argtypes = []
@@ -176,6 +206,38 @@ def dwt2_inverse_batch(images, count, ext, opt: Options | None, workspace, works
     return _lib.dwt2_inverse_batch(images, count, ext,
                                    ctypes.byref(opt) if opt is not None else None, workspace,
                                    workspace_bytes, stream)
+
+
+def dwt2_server_create(opt: Options | None, cfg: ServerConfig | None, arena, arena_bytes, stream):
+    """(status, handle)."""
+    h = ctypes.c_void_p()
+    st = _lib.dwt2_server_create(ctypes.byref(opt) if opt is not None else None,
+                                 ctypes.byref(cfg) if cfg is not None else None, arena,
+                                 arena_bytes, stream, ctypes.byref(h))
+    return st, h
+
+
+def dwt2_server_submit(server, request: Request):
+    """(status, ticket)."""
+    t = ctypes.c_ulonglong(0)
+    st = _lib.dwt2_server_submit(server, ctypes.byref(request) if request is not None else None,
+                                 ctypes.byref(t))
+    return st, t.value
+
+
+def dwt2_server_wait(server, ticket):
+    """(status, Completion)."""
+    c = Completion()
+    st = _lib.dwt2_server_wait(server, ticket, ctypes.byref(c))
+    return st, c
+
+
+def dwt2_server_replay(server, requests, arrival_us, count, done) -> int:
+    return _lib.dwt2_server_replay(server, requests, arrival_us, count, done)
+
+
+def dwt2_server_destroy(server) -> int:
+    return _lib.dwt2_server_destroy(server)
 
 
 # --- torch conveniences -------------------------------------------------------
@@ -306,3 +368,72 @@ def inverse_batch(coefs, wavelets, levels, norm="unit_dc", arithmetic="auto", ou
     if outs is None:
         outs = [torch.empty_like(x) for x in coefs]
     return Batch(coefs, outs, wavelets, levels, norm, arithmetic, inverse=True)(stream)
+
+
+class Server:
+    """Serving loop over an arena of `arena_bytes` device bytes (allocated here
+    with torch).  Requests are (src, dst) device tensors; the server keeps a
+    reference to both until the request is waited for."""
+
+    def __init__(self, arena_bytes, norm="unit_dc", arithmetic="auto", max_batch=0,
+                 max_inflight=0, stream=None, device=None):
+        import torch
+        device = device if device is not None else torch.device("cuda")
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        cfg = ServerConfig()
+        cfg.max_batch, cfg.max_inflight = max_batch, max_inflight
+        st, self.handle = dwt2_server_create(make_options(norm, "auto", arithmetic), cfg,
+                                             self.arena.data_ptr(), int(arena_bytes),
+                                             self.stream.cuda_stream)
+        if st != OK:
+            raise Dwt2Error(st, "dwt2_server_create")
+        self._held = {}
+
+    @staticmethod
+    def request(src, dst, wavelet, levels, inverse=False) -> Request:
+        _check_image(src)
+        _check_image(dst)
+        if src.shape != dst.shape:
+            raise ValueError("src and dst shapes differ")
+        h, w = src.shape
+        return Request(int(bool(inverse)), WAVELETS[wavelet], int(levels), w, h, src.data_ptr(),
+                       src.stride(0), dst.data_ptr(), dst.stride(0))
+
+    def submit(self, src, dst, wavelet, levels, inverse=False) -> int:
+        st, t = dwt2_server_submit(self.handle, self.request(src, dst, wavelet, levels, inverse))
+        if st != OK:
+            raise Dwt2Error(st, "dwt2_server_submit")
+        self._held[t] = (src, dst)
+        return t
+
+    def wait(self, ticket) -> Completion:
+        st, c = dwt2_server_wait(self.handle, ticket)
+        self._held.pop(ticket, None)
+        if st != OK:
+            raise Dwt2Error(st, "dwt2_server_wait")
+        return c
+
+    def replay(self, requests, arrival_us):
+        """requests: [(src, dst, wavelet, levels, inverse)]; returns the
+        Completion of each, submitted at arrival_us[i] microseconds."""
+        n = len(requests)
+        arr = (Request * max(n, 1))(*[self.request(*r) for r in requests])
+        t = (ctypes.c_double * max(n, 1))(*[float(a) for a in arrival_us])
+        done = (Completion * max(n, 1))()
+        st = dwt2_server_replay(self.handle, arr, t, n, done)
+        if st != OK:
+            raise Dwt2Error(st, "dwt2_server_replay")
+        return [done[i] for i in range(n)]
+
+    def close(self):
+        if self.handle:
+            dwt2_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -38,7 +38,7 @@ def test_version_and_status_codes_match_header():
     for name, val in [("DWT2_OK", dwt2.OK), ("DWT2_E_ARG", dwt2.E_ARG),
                       ("DWT2_E_SIZE", dwt2.E_SIZE), ("DWT2_E_UNSUPPORTED", dwt2.E_UNSUPPORTED),
                       ("DWT2_E_WORKSPACE", dwt2.E_WORKSPACE), ("DWT2_E_ALIAS", dwt2.E_ALIAS),
-                      ("DWT2_E_HIP", dwt2.E_HIP)]:
+                      ("DWT2_E_HIP", dwt2.E_HIP), ("DWT2_E_STATE", dwt2.E_STATE)]:
         assert header_define(name) == val
         assert dwt2.dwt2_status_string(val) != "unknown status"
     assert dwt2.dwt2_status_string(12345) == "unknown status"
