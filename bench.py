@@ -18,6 +18,8 @@ line:
   pyramid      per-level and five-level times of the 16384^2 9/7 pyramid
   batch        512 uneven images: batched call, HIP-graph replay, and one
                call per image (images/s, p99, fraction of 8 TB/s)
+  serve        the serving loop under a Poisson request stream at 0.8 x its
+               saturated rate: images/s, p50 / p99 latency
   cpu_baseline the FP64 CPU oracle on the host cores, forward + inverse of the
                same image
 """
@@ -53,6 +55,8 @@ def parse():
                     help="skip the per-level table of the 16384^2 five-level workload")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-image batched workload")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving-loop request stream")
     ap.add_argument("--no-copy", action="store_true",
                     help="skip the device-to-device copy (the bandwidth and counter reference)")
     return ap.parse_args()
@@ -162,6 +166,9 @@ def main():
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batch"] = batch_table(dwt2, torch, workloads, args.scheme_reps)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["serve"] = serve_table(dwt2, torch, workloads)
         torch.cuda.empty_cache()
     if not args.no_copy:
         out["copy_GBs"] = copy_bandwidth(torch, dev)
@@ -356,6 +363,50 @@ def batch_table(dwt2, torch, workloads, reps):
     torch.cuda.synchronize()
     rt = max(float((z - x).abs().max()) for x, z in zip(xs, zs))
     out["round_trip_max_abs"] = rt
+    return out
+
+
+def serve_table(dwt2, torch, workloads, n_requests=11000, warm=1000, n_slots=512):
+    """Serving loop under a Poisson request stream (forward or inverse, sides
+    log-uniform in [64, 8192], 1-6 levels).  Requests cycle over n_slots
+    distinct (input, output) buffer pairs.  First the saturated rate (all
+    requests arriving at once), then 0.8 x that rate; latency is submission to
+    observed completion, over the requests after the first `warm`."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    specs = workloads.serve_specs(n_slots)
+    slots = []
+    for i, (inverse, w, h, wav, lev) in enumerate(specs):
+        x = torch.from_numpy(workloads.batch_image(i, w, h, seed=4)).to(dev).float()
+        if inverse:  # coefficients of the image as input
+            x = dwt2.forward(x, wav, lev)
+        slots.append((x, torch.empty_like(x), wav, lev, inverse))
+    reqs = [slots[i % n_slots] for i in range(n_requests)]
+    mean_px = sum(s[0].numel() for s in slots) / n_slots
+    out = {"workload": f"{n_requests} requests over {n_slots} buffer slots: fwd/inv p=1/2, sides "
+                       f"log-uniform [64, 8192], cdf53/cdf97, 1-6 levels (seed 4)",
+           "mean_pixels_per_request": round(mean_px)}
+    with dwt2.Server(4 << 30, max_batch=256, max_inflight=2) as srv:
+        srv.replay(reqs[:warm], [0.0] * warm)
+        t0 = time.perf_counter()
+        done = srv.replay(reqs, [0.0] * n_requests)
+        sat = n_requests / (time.perf_counter() - t0)
+        assert all(c.status == dwt2.OK for c in done)
+        rate = 0.8 * sat
+        arrivals = workloads.poisson_arrivals(n_requests, rate)
+        t0 = time.perf_counter()
+        done = srv.replay(reqs, arrivals)
+        elapsed = time.perf_counter() - t0
+    assert all(c.status == dwt2.OK for c in done)
+    lat = np.sort(np.array([c.latency_us for c in done[warm:]]))
+    q = np.array([c.queue_us for c in done[warm:]])
+    out.update({"saturated_images_per_s": round(sat, 1),
+                "saturated_Gpixel_s": round(sat * mean_px / 1e9, 2),
+                "offered_rate_per_s": round(rate, 1),
+                "achieved_images_per_s": round(n_requests / elapsed, 1),
+                "p50_latency_us": round(float(np.percentile(lat, 50)), 1),
+                "p99_latency_us": round(float(np.percentile(lat, 99)), 1),
+                "mean_queue_us": round(float(q.mean()), 1)})
     return out
 
 

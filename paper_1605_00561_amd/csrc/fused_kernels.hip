@@ -103,32 +103,24 @@ __device__ __forceinline__ T &seam(Seams<T> &s, int b, int comp, int w, int c)
     return s.v[b][comp][w][c + 1];
 }
 
-// T_{P1} then T^H_{P0}, T^V_{P0} on one quadruple (neighbours pre-step).
+// T_{P1} on one quadruple: the neighbour part of the spatial predict, from
+// pre-step neighbour values (right LL, LH; lower LL, HL; lower-right LL).
 template <typename T>
 __device__ __forceinline__ void predict_q(T (&q)[4], T llr, T lld, T lldr, T hld, T lhr, T p, T p2)
 {
-    T &ll = q[LL], &hl = q[HL], &lh = q[LH], &hh = q[HH];
-    hl = mad(p, llr, hl);
-    lh = mad(p, lld, lh);
-    hh = mad(p2, lldr, mad(p, hld, mad(p, lhr, hh)));
-    hl = mad(p, ll, hl);
-    hh = mad(p, lh, hh);
-    lh = mad(p, ll, lh);
-    hh = mad(p, hl, hh);
+    q[HL] = mad(p, llr, q[HL]);
+    q[LH] = mad(p, lld, q[LH]);
+    q[HH] = mad(p2, lldr, mad(p, hld, mad(p, lhr, q[HH])));
 }
 
-// S_{U1} then S^H_{U0}, S^V_{U0} on one quadruple (neighbours pre-step).
+// S_{U1} on one quadruple: the neighbour part of the spatial update, from
+// pre-step neighbour values (left HL, HH; upper LH, HH; upper-left HH).
 template <typename T>
 __device__ __forceinline__ void update_q(T (&q)[4], T hll, T lhu, T hhul, T hhu, T hhl, T u, T u2)
 {
-    T &ll = q[LL], &hl = q[HL], &lh = q[LH], &hh = q[HH];
-    ll = mad(u, hll, mad(u, lhu, mad(u2, hhul, ll)));
-    hl = mad(u, hhu, hl);
-    lh = mad(u, hhl, lh);
-    ll = mad(u, hl, ll);
-    lh = mad(u, hh, lh);
-    ll = mad(u, lh, ll);
-    hl = mad(u, hh, hl);
+    q[LL] = mad(u, hll, mad(u, lhu, mad(u2, hhul, q[LL])));
+    q[HL] = mad(u, hhu, q[HL]);
+    q[LH] = mad(u, hhl, q[LH]);
 }
 
 // T_{-P1} on one quadruple.

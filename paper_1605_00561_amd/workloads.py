@@ -18,6 +18,11 @@ unspecified, so these synthetic images stand in for them):
                       probability 1/2, levels uniform in {3, 4, 5, 6}.
 * ``batch_image``     the pixels of image i of a batch: integers uniform in
                       [0, 255], drawn from the seed sequence (seed, i).
+* ``serve_specs``     a request stream: direction forward or inverse with
+                      probability 1/2, width and height independent and
+                      log-uniform in [64, 8192] (rounded, odd sizes allowed),
+                      wavelet 5/3 or 9/7 with probability 1/2, levels uniform
+                      in 1..6; ``poisson_arrivals`` gives exponential gaps.
 """
 from __future__ import annotations
 
@@ -104,3 +109,25 @@ def batch_image(i: int, width: int, height: int, seed: int = 3) -> np.ndarray:
     host memory small; cast to FP32 on the device)."""
     rng = np.random.default_rng([seed, i])
     return rng.integers(0, 256, size=(height, width), dtype=np.uint8)
+
+
+def serve_specs(n: int, seed: int = 4):
+    """[(inverse, width, height, wavelet, levels)] of a request stream."""
+    rng = np.random.default_rng(seed)
+    out = []
+    lo, hi = np.log(64.0), np.log(8192.0)
+    for _ in range(n):
+        inverse = bool(rng.random() < 0.5)
+        w = int(round(float(np.exp(rng.uniform(lo, hi)))))
+        h = int(round(float(np.exp(rng.uniform(lo, hi)))))
+        wav = "cdf53" if rng.random() < 0.5 else "cdf97"
+        lev = int(rng.integers(1, 7))
+        out.append((inverse, w, h, wav, lev))
+    return out
+
+
+def poisson_arrivals(n: int, rate_per_s: float, seed: int = 5) -> np.ndarray:
+    """Arrival times in microseconds of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1e6 / rate_per_s, size=n)
+    return np.cumsum(gaps) - gaps[0]
