@@ -304,13 +304,10 @@ __device__ __forceinline__ void inverse_tile(T (&q)[RB][4], Seams<T> &sm, int w,
     }
 }
 
-__device__ __forceinline__ void store_nt(float *p, float v) { __builtin_nontemporal_store(v, p); }
-__device__ __forceinline__ void store_nt2(float *p, float a, float b)
-{
-    typedef float f2 __attribute__((ext_vector_type(2)));
-    f2 v = {a, b};
-    __builtin_nontemporal_store(v, (f2 *)p);
-}
+// Plain stores: measured faster here than non-temporal ones, which slowed the
+// forward's four-quadrant dword stores by a third.
+__device__ __forceinline__ void store1(float *p, float v) { *p = v; }
+__device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)p = make_float2(a, b); }
 
 // Horizontal fast path: the tile's 128 pixel columns lie inside the image and
 // rows are 8-byte aligned, so each pixel-row pair is one float2 per lane.
@@ -359,14 +356,14 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, Seams<T> &sm, int tc,
     for (int j = 0; j < RB; j++) {
         const int r = w * RB + j, qr = qr0 + j;
         if (r < HQ || r >= TY - HQ || qr >= QH) continue;
-        store_nt(a.ll + (ptrdiff_t)qr * a.ll_pitch + qc,
+        store1(a.ll + (ptrdiff_t)qr * a.ll_pitch + qc,
                  (float)(q[j][LL] * (T)a.s.ll + (T)cll));
         float *drow = a.det + (ptrdiff_t)qr * a.det_pitch;
-        if (qc < WH) store_nt(drow + QW + qc, (float)q[j][HL]);
+        if (qc < WH) store1(drow + QW + qc, (float)q[j][HL]);
         if (qr < HHr) {
             float *hrow = a.det + (ptrdiff_t)(QH + qr) * a.det_pitch;
-            store_nt(hrow + qc, (float)q[j][LH]);
-            if (qc < WH) store_nt(hrow + QW + qc, (float)(q[j][HH] * (T)a.s.hh));
+            store1(hrow + qc, (float)q[j][LH]);
+            if (qc < WH) store1(hrow + QW + qc, (float)(q[j][HH] * (T)a.s.hh));
         }
     }
 }
@@ -416,14 +413,14 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, Seams<T> &sm, int tc,
         const float v0 = (float)(q[j][LL] + cc), v1 = (float)(q[j][HL] + cc);
         const float v2 = (float)(q[j][LH] + cc), v3 = (float)(q[j][HH] + cc);
         if (VEC) {
-            store_nt2(o0 + px, v0, v1);
-            if (2 * qr + 1 < H) store_nt2(o0 + a.out_pitch + px, v2, v3);
+            store2(o0 + px, v0, v1);
+            if (2 * qr + 1 < H) store2(o0 + a.out_pitch + px, v2, v3);
         } else {
-            store_nt(o0 + px, v0);
-            if (px + 1 < W) store_nt(o0 + px + 1, v1);
+            store1(o0 + px, v0);
+            if (px + 1 < W) store1(o0 + px + 1, v1);
             if (2 * qr + 1 < H) {
-                store_nt(o0 + a.out_pitch + px, v2);
-                if (px + 1 < W) store_nt(o0 + a.out_pitch + px + 1, v3);
+                store1(o0 + a.out_pitch + px, v2);
+                if (px + 1 < W) store1(o0 + a.out_pitch + px + 1, v3);
             }
         }
     }

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_1605_00561_amd import workloads as wl
-from test_gpu_parity import check, dev, empty_dev, exact_expected, to_dev, to_host
+from test_gpu_parity import check, dev, empty_dev, exact_expected, paper_ratio, to_dev, to_host
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -65,8 +65,12 @@ def test_mixed_batch_equals_single_calls(norm, arith):
         assert torch.equal(z, single(y, wav, lev, norm, arith, inverse=True)), "inverse " + what
         if arith == "fp32":
             got = to_host(y)
-            ref = oracle.forward(hosts[i].astype(np.float64), wav, lev, norm)
-            check(got, ref, exact_expected(wav, lev, norm), "fwd " + what)
+            ref = oracle.forward(hosts[i].astype(np.float64), wav, lev, "unit_dc")
+            # PAPER's LL doubles per level (2^7 x 255 at level 7, where one FP32
+            # ulp already exceeds 1e-3): compare it in UNIT_DC scale, dividing
+            # each subband by its exact power-of-two factor.
+            scale = paper_ratio(x.shape[1], x.shape[0], lev) if norm == "paper" else 1.0
+            check(got / scale, ref, exact_expected(wav, lev, norm), "fwd " + what)
             check(to_host(z), oracle.inverse(got, wav, lev, norm), exact_expected(wav, lev, norm),
                   "inv " + what)
 

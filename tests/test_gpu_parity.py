@@ -149,15 +149,12 @@ def test_schemes_agree_bitwise_on_5_3(scheme):
     assert np.array_equal(ref, got)
 
 
-@pytest.mark.parametrize("wav", WAVS)
-def test_normalisation_relation_bitwise(wav):
-    """PAPER = UNIT_DC x 2^(k-1) x {2, 1, 1, 1/2} per subband, bit for bit."""
-    x = wl.uniform_u8(301, 187, seed=105)
-    lev = 4
-    u = to_host(dwt2.forward(to_dev(x), wav, lev, "unit_dc"))
-    p = to_host(dwt2.forward(to_dev(x), wav, lev, "paper"))
-    ratio = np.ones_like(u)
-    wk, hk = 301, 187
+def paper_ratio(w, h, lev):
+    """PAPER / UNIT_DC per coefficient of a `lev`-level Mallat layout: at level
+    k the subbands differ by 2^(k-1) x {2 for LL, 1 for HL and LH, 1/2 for HH}
+    (the header's normalisation relation), all exact powers of two."""
+    ratio = np.ones((h, w))
+    wk, hk = w, h
     for k in range(1, lev + 1):
         wl_, hl_ = (wk + 1) // 2, (hk + 1) // 2
         f = 2.0 ** (k - 1)
@@ -166,7 +163,17 @@ def test_normalisation_relation_bitwise(wav):
         ratio[hl_:hk, wl_:wk] = f / 2
         ratio[:hl_, :wl_] = 2 * f
         wk, hk = wl_, hl_
-    assert np.array_equal(p, u * ratio)
+    return ratio
+
+
+@pytest.mark.parametrize("wav", WAVS)
+def test_normalisation_relation_bitwise(wav):
+    """PAPER = UNIT_DC x 2^(k-1) x {2, 1, 1, 1/2} per subband, bit for bit."""
+    x = wl.uniform_u8(301, 187, seed=105)
+    lev = 4
+    u = to_host(dwt2.forward(to_dev(x), wav, lev, "unit_dc"))
+    p = to_host(dwt2.forward(to_dev(x), wav, lev, "paper"))
+    assert np.array_equal(p, u * paper_ratio(301, 187, lev))
 
 
 def test_constant_and_ramp_images():
@@ -185,9 +192,12 @@ def test_constant_and_ramp_images():
 
 
 # FP64 lifting in the fused kernel: the only rounding left is the FP32 store
-# of each level's output (and its reload by the next level), so the result is
-# held to a bar near the FP32 resolution of [0, 255] data.
-FP64_BAR = (4e-5, 1e-7)
+# of each level's output and its reload by the next level.  Half an FP32 ulp
+# is 7.6e-6 for |y| < 256 and 3.1e-5 for |y| < 1024 (9/7 details of [0, 255]
+# data reach several hundred), and the LL rounding of each level passes
+# through the lifting gain of every later level (up to 7 here), so the bar is
+# 1e-4 max-abs -- ten times below the FP32 bar -- and 1e-7 relative L2.
+FP64_BAR = (1e-4, 1e-7)
 
 
 @pytest.mark.parametrize("wav", WAVS)
