@@ -13,8 +13,9 @@ line:
                timed with HIP events on the launch stream
   schemes      per-scheme forward / inverse Gpixel/s and % of 8 TB/s: the fused
                register-blocked Monolithic*, and in the LDS tile harness
-               Monolithic* (2 barriers per pair), separable Sweldens (4) and
-               Iwahashi (3), plus the row-column separable two-pass kernels
+               Monolithic* and Monolithic (2 barriers per pair), separable
+               Sweldens (4), Iwahashi, Iwahashi*, Explosive, Explosive* (3) and
+               Polyphase* (1), plus the row-column separable two-pass kernels
   pyramid      per-level and five-level times of the 16384^2 9/7 pyramid
   batch        512 uneven images: batched call, HIP-graph replay, and one
                call per image (images/s, p99, fraction of 8 TB/s)
@@ -182,8 +183,8 @@ def main():
 def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
     stream = torch.cuda.current_stream()
     table = {}
-    for name in ("monolithic*", "monolithic*:fp64", "monolithic*-tile", "sweldens", "iwahashi",
-                 "rowcol"):
+    for name in ("monolithic*", "monolithic*:fp64", "monolithic*-tile", "monolithic", "sweldens",
+                 "iwahashi", "iwahashi*", "explosive", "explosive*", "polyphase*", "rowcol"):
         scheme, _, arith = name.partition(":")
         arith = arith or "auto"
         ws = None

@@ -97,6 +97,14 @@ typedef enum dwt2_norm { DWT2_NORM_UNIT_DC = 0, DWT2_NORM_PAPER = 1 } dwt2_norm;
  *   IWAHASHI              earlier non-separable T^I_P | R^I_{P,U} | S^I_U in the
  *                         tile harness, 3 barriers per pair (Sec. 2).
  *   ROWCOL                separable row pass then column pass through memory.
+ * The remaining variants of the paper, all in the tile harness:
+ *   MONOLITHIC            unsplit T_P | S_U (Sec. 3), 2 barriers per pair.
+ *   EXPLOSIVE             T^E_P | R^E_{P,U} | S^E_U (Sec. 3), 3 barriers.
+ *   EXPLOSIVE_STAR        Explosive with the scalar parts P0, U0 split off
+ *                         (Sec. 4), 3 barriers.
+ *   IWAHASHI_STAR         Iwahashi with P0, U0 split off (Sec. 4), 3 barriers.
+ *   POLYPHASE_STAR        scalar P0 parts, then N_{P1,U1} as one step, then
+ *                         scalar U0 parts (Sec. 4): 1 barrier per pair.
  */
 typedef enum dwt2_scheme {
     DWT2_SCHEME_AUTO = 0,
@@ -104,7 +112,12 @@ typedef enum dwt2_scheme {
     DWT2_SCHEME_SWELDENS = 2,
     DWT2_SCHEME_IWAHASHI = 3,
     DWT2_SCHEME_ROWCOL = 4,
-    DWT2_SCHEME_MONOLITHIC_STAR_TILE = 5
+    DWT2_SCHEME_MONOLITHIC_STAR_TILE = 5,
+    DWT2_SCHEME_MONOLITHIC = 6,
+    DWT2_SCHEME_EXPLOSIVE = 7,
+    DWT2_SCHEME_EXPLOSIVE_STAR = 8,
+    DWT2_SCHEME_IWAHASHI_STAR = 9,
+    DWT2_SCHEME_POLYPHASE_STAR = 10
 } dwt2_scheme;
 
 /*

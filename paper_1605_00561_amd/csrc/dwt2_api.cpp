@@ -48,7 +48,7 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     }
     if (c->arithmetic < DWT2_ARITH_AUTO || c->arithmetic > DWT2_ARITH_FP64) return DWT2_E_UNSUPPORTED;
     if (c->norm != DWT2_NORM_UNIT_DC && c->norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
-    if (c->scheme < DWT2_SCHEME_AUTO || c->scheme > DWT2_SCHEME_MONOLITHIC_STAR_TILE)
+    if (c->scheme < DWT2_SCHEME_AUTO || c->scheme > DWT2_SCHEME_POLYPHASE_STAR)
         return DWT2_E_UNSUPPORTED;
     if (c->scheme == DWT2_SCHEME_AUTO) c->scheme = DWT2_SCHEME_MONOLITHIC_STAR;
     // FP64 lifting is implemented by the fused kernel only.

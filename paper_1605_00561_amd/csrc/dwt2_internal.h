@@ -8,9 +8,12 @@
 namespace dwt2 {
 
 enum Wavelet : int { CDF53 = 0, CDF97 = 1 };
-// Scheme ids as in dwt2.h; MONO_STAR is the fused register-blocked kernel and
-// MONO_STAR_TILE the same steps in the LDS tile harness.
-enum Scheme : int { MONO_STAR = 1, SWELDENS = 2, IWAHASHI = 3, ROWCOL = 4, MONO_STAR_TILE = 5 };
+// Scheme ids as in dwt2.h; MONO_STAR is the fused register-blocked kernel,
+// ROWCOL the two-pass kernels, all others run in the LDS tile harness.
+enum Scheme : int {
+    MONO_STAR = 1, SWELDENS = 2, IWAHASHI = 3, ROWCOL = 4, MONO_STAR_TILE = 5,
+    MONOLITHIC = 6, EXPLOSIVE = 7, EXPLOSIVE_STAR = 8, IWAHASHI_STAR = 9, POLYPHASE_STAR = 10
+};
 
 // Lifting pairs in the L = x[2n], H = x[2n+1] phase.  The paper's operators
 // (Sec. 5) P(z) = p (1 + z^-1) and U(z) = u (1 + z) become, after the index

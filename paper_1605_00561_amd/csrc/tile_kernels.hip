@@ -221,11 +221,13 @@ __device__ __forceinline__ void swel_SV(float *lds, int A, Quads &q, int lane, i
 }
 
 // ---------------------------------------------------------------------------
-// Iwahashi steps (non-separable, three per pair).  sg = +1 forward, -1 inverse:
-// the inverse of each step subtracts the same terms (each reads components the
-// step does not modify), except that the product terms keep their sign rule.
+// Iwahashi steps (non-separable, three per pair).  Each step reads only
+// components it does not modify, so its inverse subtracts the same terms
+// (the product terms flip sign with the others).  FULL: the whole operators
+// P = p (1 + z), U = u (1 + z^-1) (Iwahashi); otherwise only the neighbour
+// parts P1 = p z, U1 = u z^-1 (Iwahashi*, whose scalar parts run locally).
 // ---------------------------------------------------------------------------
-template <bool INV>
+template <bool FULL, bool INV>
 __device__ __forceinline__ void iwa_T(float *lds, int A, Quads &q, int lane, int wv, float p)
 {   // HH += P P* LL + P* HL + P LH   (reads LL at c+1, r+1, (r+1,c+1); HL at r+1; LH at c+1)
     const float sp = INV ? -p : p;
@@ -233,15 +235,19 @@ __device__ __forceinline__ void iwa_T(float *lds, int A, Quads &q, int lane, int
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
         const int r = j * NWAVES + wv;
-        const float llsum = (q.v[j][LL] + cell(lds, A + 0, r, lane + 1)) +
-                            (cell(lds, A + 0, r + 1, lane) + cell(lds, A + 0, r + 1, lane + 1));
+        const float lldr = cell(lds, A + 0, r + 1, lane + 1);
+        const float llsum = FULL ? (q.v[j][LL] + cell(lds, A + 0, r, lane + 1)) +
+                                       (cell(lds, A + 0, r + 1, lane) + lldr)
+                                 : lldr;
+        const float hl = FULL ? q.v[j][HL] + cell(lds, A + 1, r + 1, lane) : cell(lds, A + 1, r + 1, lane);
+        const float lh = FULL ? q.v[j][LH] + cell(lds, A + 2, r, lane + 1) : cell(lds, A + 2, r, lane + 1);
         float hh = q.v[j][HH];
-        hh = fmaf(sp, q.v[j][LH] + cell(lds, A + 2, r, lane + 1), hh);
-        hh = fmaf(sp, q.v[j][HL] + cell(lds, A + 1, r + 1, lane), hh);
+        hh = fmaf(sp, lh, hh);
+        hh = fmaf(sp, hl, hh);
         q.v[j][HH] = fmaf(sp2, llsum, hh);
     }
 }
-template <bool INV>
+template <bool FULL, bool INV>
 __device__ __forceinline__ void iwa_R(float *lds, int B, Quads &q, int lane, int wv, float p, float u)
 {   // HL += P LL + U* HH; LH += P* LL + U HH   (reads LL at c+1, r+1; HH at r-1, c-1)
     const float sp = INV ? -p : p;
@@ -249,14 +255,14 @@ __device__ __forceinline__ void iwa_R(float *lds, int B, Quads &q, int lane, int
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
         const int r = j * NWAVES + wv;
-        const float ll = q.v[j][LL], hh = q.v[j][HH];
+        const float ll = FULL ? q.v[j][LL] : 0.0f, hh = FULL ? q.v[j][HH] : 0.0f;
         q.v[j][HL] = fmaf(su, hh + cell(lds, B + 1, r - 1, lane),
                           fmaf(sp, ll + cell(lds, B + 0, r, lane + 1), q.v[j][HL]));
         q.v[j][LH] = fmaf(su, hh + cell(lds, B + 1, r, lane - 1),
                           fmaf(sp, ll + cell(lds, B + 0, r + 1, lane), q.v[j][LH]));
     }
 }
-template <bool INV>
+template <bool FULL, bool INV>
 __device__ __forceinline__ void iwa_S(float *lds, int A, Quads &q, int lane, int wv, float u)
 {   // LL += U HL + U* LH - U U* HH   (reads HL at c-1; LH at r-1; HH at c-1, r-1, (r-1,c-1))
     const float su = INV ? -u : u;
@@ -264,12 +270,180 @@ __device__ __forceinline__ void iwa_S(float *lds, int A, Quads &q, int lane, int
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
         const int r = j * NWAVES + wv;
-        const float hhsum = (q.v[j][HH] + cell(lds, A + 2, r, lane - 1)) +
-                            (cell(lds, A + 2, r - 1, lane) + cell(lds, A + 2, r - 1, lane - 1));
+        const float hhul = cell(lds, A + 2, r - 1, lane - 1);
+        const float hhsum = FULL ? (q.v[j][HH] + cell(lds, A + 2, r, lane - 1)) +
+                                       (cell(lds, A + 2, r - 1, lane) + hhul)
+                                 : hhul;
+        const float hl = FULL ? q.v[j][HL] + cell(lds, A + 0, r, lane - 1) : cell(lds, A + 0, r, lane - 1);
+        const float lh = FULL ? q.v[j][LH] + cell(lds, A + 1, r - 1, lane) : cell(lds, A + 1, r - 1, lane);
         float ll = q.v[j][LL];
-        ll = fmaf(su, q.v[j][HL] + cell(lds, A + 0, r, lane - 1), ll);
-        ll = fmaf(su, q.v[j][LH] + cell(lds, A + 1, r - 1, lane), ll);
+        ll = fmaf(su, hl, ll);
+        ll = fmaf(su, lh, ll);
         q.v[j][LL] = fmaf(su2, hhsum, ll);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Explosive steps (Sec. 3): the predict pushes data out of LL (T^E), the
+// update out of HH (S^E), and R^E joins them.  Like Iwahashi's, each step
+// reads only components it leaves unchanged.  FULL as for Iwahashi
+// (Explosive / Explosive*).
+// ---------------------------------------------------------------------------
+template <bool FULL, bool INV>
+__device__ __forceinline__ void exp_T(float *lds, int A, Quads &q, int lane, int wv, float p)
+{   // HL += P LL; LH += P* LL; HH -= P P* LL   (reads LL at c+1, r+1, (r+1,c+1))
+    const float sp = INV ? -p : p;
+    const float sp2 = INV ? p * p : -(p * p);
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float ll = FULL ? q.v[j][LL] : 0.0f;
+        const float llr = cell(lds, A, r, lane + 1), lld = cell(lds, A, r + 1, lane);
+        const float lldr = cell(lds, A, r + 1, lane + 1);
+        q.v[j][HL] = fmaf(sp, ll + llr, q.v[j][HL]);
+        q.v[j][LH] = fmaf(sp, ll + lld, q.v[j][LH]);
+        q.v[j][HH] = fmaf(sp2, FULL ? (ll + llr) + (lld + lldr) : lldr, q.v[j][HH]);
+    }
+}
+template <bool FULL, bool INV>
+__device__ __forceinline__ void exp_R(float *lds, int B, Quads &q, int lane, int wv, float p, float u)
+{   // LL += U HL + U* LH; HH += P* HL + P LH   (reads HL at c-1, r+1; LH at r-1, c+1)
+    const float sp = INV ? -p : p;
+    const float su = INV ? -u : u;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float hl = FULL ? q.v[j][HL] : 0.0f, lh = FULL ? q.v[j][LH] : 0.0f;
+        q.v[j][LL] = fmaf(su, lh + cell(lds, B + 1, r - 1, lane),
+                          fmaf(su, hl + cell(lds, B + 0, r, lane - 1), q.v[j][LL]));
+        q.v[j][HH] = fmaf(sp, lh + cell(lds, B + 1, r, lane + 1),
+                          fmaf(sp, hl + cell(lds, B + 0, r + 1, lane), q.v[j][HH]));
+    }
+}
+template <bool FULL, bool INV>
+__device__ __forceinline__ void exp_S(float *lds, int A, Quads &q, int lane, int wv, float u)
+{   // LL += U U* HH; HL += U* HH; LH += U HH   (reads HH at c-1, r-1, (r-1,c-1))
+    const float su = INV ? -u : u;
+    const float su2 = INV ? -(u * u) : u * u;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float hh = FULL ? q.v[j][HH] : 0.0f;
+        const float hhl = cell(lds, A, r, lane - 1), hhu = cell(lds, A, r - 1, lane);
+        const float hhul = cell(lds, A, r - 1, lane - 1);
+        q.v[j][LL] = fmaf(su2, FULL ? (hh + hhl) + (hhu + hhul) : hhul, q.v[j][LL]);
+        q.v[j][HL] = fmaf(su, hh + hhu, q.v[j][HL]);
+        q.v[j][LH] = fmaf(su, hh + hhl, q.v[j][LH]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Unsplit Monolithic (Sec. 3): T_P = T^V_P T^H_P and S_U = S^V_U S^H_U each as
+// one spatial step on pre-step values.  The inverse of T_P is T_{-P} (the two
+// separable factors commute), and likewise for S_U.
+// ---------------------------------------------------------------------------
+template <bool INV>
+__device__ __forceinline__ void mono_T_full(float *lds, int A, Quads &q, int lane, int wv, float p)
+{   // HL += P LL; LH += P* LL; HH += P P* LL + P* HL + P LH
+    const float sp = INV ? -p : p, p2 = p * p;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float ll = q.v[j][LL], llr = cell(lds, A + 0, r, lane + 1);
+        const float lld = cell(lds, A + 0, r + 1, lane), lldr = cell(lds, A + 0, r + 1, lane + 1);
+        const float hl = q.v[j][HL], lh = q.v[j][LH];
+        q.v[j][HH] = fmaf(p2, (ll + llr) + (lld + lldr),
+                          fmaf(sp, hl + cell(lds, A + 1, r + 1, lane),
+                               fmaf(sp, lh + cell(lds, A + 2, r, lane + 1), q.v[j][HH])));
+        q.v[j][HL] = fmaf(sp, ll + llr, hl);
+        q.v[j][LH] = fmaf(sp, ll + lld, lh);
+    }
+}
+template <bool INV>
+__device__ __forceinline__ void mono_S_full(float *lds, int B, Quads &q, int lane, int wv, float u)
+{   // LL += U HL + U* LH + U U* HH; HL += U* HH; LH += U HH
+    const float su = INV ? -u : u, u2 = u * u;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float hh = q.v[j][HH], hhl = cell(lds, B + 2, r, lane - 1);
+        const float hhu = cell(lds, B + 2, r - 1, lane), hhul = cell(lds, B + 2, r - 1, lane - 1);
+        const float hl = q.v[j][HL], lh = q.v[j][LH];
+        q.v[j][LL] = fmaf(u2, (hh + hhl) + (hhu + hhul),
+                          fmaf(su, hl + cell(lds, B + 0, r, lane - 1),
+                               fmaf(su, lh + cell(lds, B + 1, r - 1, lane), q.v[j][LL])));
+        q.v[j][HL] = fmaf(su, hh + hhu, hl);
+        q.v[j][LH] = fmaf(su, hh + hhl, lh);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Polyphase* (Sec. 4): the neighbour parts of one whole pair as the single
+// 4x4 step N_{P1,U1}, one barrier per pair.  With P1 = p z and U1 = u z^-1,
+// V1 = P1 U1 + 1 = 1 + p u is a scalar.  The inverse is the single step
+// N_{P1,U1}^{-1} = T_{-P1} S_{-U1} (one matrix, one barrier as well).
+// ---------------------------------------------------------------------------
+template <bool INV>
+__device__ __forceinline__ void poly_N(float *lds, int A, Quads &q, int lane, int wv, float p, float u)
+{
+    const float v = fmaf(p, u, 1.0f), pu = p * u, p2 = p * p, u2 = u * u;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int r = j * NWAVES + wv;
+        const float llr = cell(lds, A + 0, r, lane + 1), lld = cell(lds, A + 0, r + 1, lane);
+        const float lldr = cell(lds, A + 0, r + 1, lane + 1);
+        const float hll = cell(lds, A + 1, r, lane - 1), hld = cell(lds, A + 1, r + 1, lane);
+        const float hldl = cell(lds, A + 1, r + 1, lane - 1);
+        const float lhu = cell(lds, A + 2, r - 1, lane), lhr = cell(lds, A + 2, r, lane + 1);
+        const float lhur = cell(lds, A + 2, r - 1, lane + 1);
+        const float hhul = cell(lds, A + 3, r - 1, lane - 1), hhu = cell(lds, A + 3, r - 1, lane);
+        const float hhl = cell(lds, A + 3, r, lane - 1);
+        const float ll = q.v[j][LL], hl = q.v[j][HL], lh = q.v[j][LH], hh = q.v[j][HH];
+        if (!INV) {
+            // LL' = V^2 LL + V u HL[c-1] + V u LH[r-1] + u^2 HH[r-1][c-1]
+            q.v[j][LL] = fmaf(u2, hhul, fmaf(v * u, hll + lhu, v * v * ll));
+            // HL' = V p LL[c+1] + V HL + u p LH[r-1][c+1] + u HH[r-1]
+            q.v[j][HL] = fmaf(u, hhu, fmaf(pu, lhur, v * fmaf(p, llr, hl)));
+            // LH' = V p LL[r+1] + p u HL[r+1][c-1] + V LH + u HH[c-1]
+            q.v[j][LH] = fmaf(u, hhl, fmaf(pu, hldl, v * fmaf(p, lld, lh)));
+            // HH' = p^2 LL[r+1][c+1] + p HL[r+1] + p LH[c+1] + HH
+            q.v[j][HH] = fmaf(p2, lldr, fmaf(p, hld + lhr, hh));
+        } else {
+            // LL' = LL - u HL[c-1] - u LH[r-1] + u^2 HH[r-1][c-1]
+            q.v[j][LL] = fmaf(u2, hhul, fmaf(-u, hll + lhu, ll));
+            // HL' = -p LL[c+1] + V HL + p u LH[r-1][c+1] - V u HH[r-1]
+            q.v[j][HL] = fmaf(-v * u, hhu, fmaf(pu, lhur, fmaf(v, hl, -p * llr)));
+            // LH' = -p LL[r+1] + p u HL[r+1][c-1] + V LH - V u HH[c-1]
+            q.v[j][LH] = fmaf(-v * u, hhl, fmaf(pu, hldl, fmaf(v, lh, -p * lld)));
+            // HH' = p^2 LL[r+1][c+1] - V p (HL[r+1] + LH[c+1]) + V^2 HH
+            q.v[j][HH] = fmaf(p2, lldr, fmaf(-v * p, hld + lhr, v * v * hh));
+        }
+    }
+}
+
+// Scalar parts T^H_{P0} then T^V_{P0}, and S^H_{U0} then S^V_{U0}: local to
+// the quadruple, no barrier (the starred schemes run them around the
+// neighbour steps).
+__device__ __forceinline__ void predict_local(Quads &q, float p)
+{
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        float &ll = q.v[j][LL], &hl = q.v[j][HL], &lh = q.v[j][LH], &hh = q.v[j][HH];
+        hl = fmaf(p, ll, hl);  // T^H_{P0}
+        hh = fmaf(p, lh, hh);
+        lh = fmaf(p, ll, lh);  // T^V_{P0}
+        hh = fmaf(p, hl, hh);
+    }
+}
+__device__ __forceinline__ void update_local(Quads &q, float u)
+{
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        float &ll = q.v[j][LL], &hl = q.v[j][HL], &lh = q.v[j][LH], &hh = q.v[j][HH];
+        ll = fmaf(u, hl, ll);  // S^H_{U0}
+        lh = fmaf(u, hh, lh);
+        ll = fmaf(u, lh, ll);  // S^V_{U0}
+        hl = fmaf(u, hh, hl);
     }
 }
 
@@ -277,11 +451,20 @@ __device__ __forceinline__ void iwa_S(float *lds, int A, Quads &q, int lane, int
 // The transform of one tile held in registers.  `step` counts spatial steps so
 // that consecutive steps use alternating LDS buffers.
 // ---------------------------------------------------------------------------
+// LDS planes one spatial step publishes (one buffer); two buffers alternate.
+template <int SCH>
+constexpr int buf_planes()
+{
+    return SCH == SWELDENS || SCH == EXPLOSIVE || SCH == EXPLOSIVE_STAR ? 2
+           : SCH == POLYPHASE_STAR                                     ? 4
+                                                                       : 3;
+}
+
 template <int WAV, int SCH, bool INV>
 __device__ __forceinline__ void transform_tile(float *lds, Quads &q, int lane, int wv)
 {
     using L = Lift<WAV>;
-    constexpr int BUF = (SCH == SWELDENS) ? 2 : 3;  // planes per buffer
+    constexpr int BUF = buf_planes<SCH>();
     int step = 0;
     auto buf = [&]() { return (step++ & 1) * BUF; };
 #define SYNC() __syncthreads()
@@ -355,21 +538,114 @@ __device__ __forceinline__ void transform_tile(float *lds, Quads &q, int lane, i
             if (!INV) {
                 A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
                 publish<LH>(lds, A + 2, q, lane, wv);
-                SYNC(); iwa_T<false>(lds, A, q, lane, wv, p);
+                SYNC(); iwa_T<true, false>(lds, A, q, lane, wv, p);
                 A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
-                SYNC(); iwa_R<false>(lds, A, q, lane, wv, p, u);
+                SYNC(); iwa_R<true, false>(lds, A, q, lane, wv, p, u);
                 A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
                 publish<HH>(lds, A + 2, q, lane, wv);
-                SYNC(); iwa_S<false>(lds, A, q, lane, wv, u);
+                SYNC(); iwa_S<true, false>(lds, A, q, lane, wv, u);
             } else {
                 A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
                 publish<HH>(lds, A + 2, q, lane, wv);
-                SYNC(); iwa_S<true>(lds, A, q, lane, wv, u);
+                SYNC(); iwa_S<true, true>(lds, A, q, lane, wv, u);
                 A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
-                SYNC(); iwa_R<true>(lds, A, q, lane, wv, p, u);
+                SYNC(); iwa_R<true, true>(lds, A, q, lane, wv, p, u);
                 A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
                 publish<LH>(lds, A + 2, q, lane, wv);
-                SYNC(); iwa_T<true>(lds, A, q, lane, wv, p);
+                SYNC(); iwa_T<true, true>(lds, A, q, lane, wv, p);
+            }
+        }
+    } else if constexpr (SCH == IWAHASHI_STAR || SCH == EXPLOSIVE || SCH == EXPLOSIVE_STAR) {
+        // Three neighbour steps per pair; the starred forms run the scalar
+        // parts T^H_{P0} T^V_{P0} before them and S^H_{U0} S^V_{U0} after
+        // (the neighbour steps do not commute with the scalar ones here).
+        constexpr bool STAR = SCH != EXPLOSIVE, FULL = !STAR;
+#pragma unroll
+        for (int kk = 0; kk < L::K; kk++) {
+            const int k = INV ? L::K - 1 - kk : kk;
+            const float p = L::p(k), u = L::u(k);
+            int A;
+            if (!INV) {
+                if (STAR) predict_local(q, p);
+                if constexpr (SCH == IWAHASHI_STAR) {
+                    A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+                    publish<LH>(lds, A + 2, q, lane, wv);
+                    SYNC(); iwa_T<false, false>(lds, A, q, lane, wv, p);
+                    A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
+                    SYNC(); iwa_R<false, false>(lds, A, q, lane, wv, p, u);
+                    A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                    publish<HH>(lds, A + 2, q, lane, wv);
+                    SYNC(); iwa_S<false, false>(lds, A, q, lane, wv, u);
+                } else {
+                    A = buf(); publish<LL>(lds, A, q, lane, wv);
+                    SYNC(); exp_T<FULL, false>(lds, A, q, lane, wv, p);
+                    A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                    SYNC(); exp_R<FULL, false>(lds, A, q, lane, wv, p, u);
+                    A = buf(); publish<HH>(lds, A, q, lane, wv);
+                    SYNC(); exp_S<FULL, false>(lds, A, q, lane, wv, u);
+                }
+                if (STAR) update_local(q, u);
+            } else {
+                if (STAR) mono_unupdate_local(q, u);
+                if constexpr (SCH == IWAHASHI_STAR) {
+                    A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                    publish<HH>(lds, A + 2, q, lane, wv);
+                    SYNC(); iwa_S<false, true>(lds, A, q, lane, wv, u);
+                    A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HH>(lds, A + 1, q, lane, wv);
+                    SYNC(); iwa_R<false, true>(lds, A, q, lane, wv, p, u);
+                    A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+                    publish<LH>(lds, A + 2, q, lane, wv);
+                    SYNC(); iwa_T<false, true>(lds, A, q, lane, wv, p);
+                } else {
+                    A = buf(); publish<HH>(lds, A, q, lane, wv);
+                    SYNC(); exp_S<FULL, true>(lds, A, q, lane, wv, u);
+                    A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                    SYNC(); exp_R<FULL, true>(lds, A, q, lane, wv, p, u);
+                    A = buf(); publish<LL>(lds, A, q, lane, wv);
+                    SYNC(); exp_T<FULL, true>(lds, A, q, lane, wv, p);
+                }
+                if (STAR) mono_unpredict_local(q, p);
+            }
+        }
+    } else if constexpr (SCH == MONOLITHIC) {
+#pragma unroll
+        for (int kk = 0; kk < L::K; kk++) {
+            const int k = INV ? L::K - 1 - kk : kk;
+            const float p = L::p(k), u = L::u(k);
+            int A;
+            if (!INV) {
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+                publish<LH>(lds, A + 2, q, lane, wv);
+                SYNC(); mono_T_full<false>(lds, A, q, lane, wv, p);
+                A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                publish<HH>(lds, A + 2, q, lane, wv);
+                SYNC(); mono_S_full<false>(lds, A, q, lane, wv, u);
+            } else {
+                A = buf(); publish<HL>(lds, A, q, lane, wv); publish<LH>(lds, A + 1, q, lane, wv);
+                publish<HH>(lds, A + 2, q, lane, wv);
+                SYNC(); mono_S_full<true>(lds, A, q, lane, wv, u);
+                A = buf(); publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+                publish<LH>(lds, A + 2, q, lane, wv);
+                SYNC(); mono_T_full<true>(lds, A, q, lane, wv, p);
+            }
+        }
+    } else if constexpr (SCH == POLYPHASE_STAR) {
+#pragma unroll
+        for (int kk = 0; kk < L::K; kk++) {
+            const int k = INV ? L::K - 1 - kk : kk;
+            const float p = L::p(k), u = L::u(k);
+            if (!INV) predict_local(q, p);
+            else mono_unupdate_local(q, u);
+            const int A = buf();
+            publish<LL>(lds, A, q, lane, wv); publish<HL>(lds, A + 1, q, lane, wv);
+            publish<LH>(lds, A + 2, q, lane, wv); publish<HH>(lds, A + 3, q, lane, wv);
+            SYNC();
+            if (!INV) {
+                poly_N<false>(lds, A, q, lane, wv, p, u);
+                update_local(q, u);
+            } else {
+                poly_N<true>(lds, A, q, lane, wv, p, u);
+                mono_unpredict_local(q, p);
             }
         }
     }
@@ -377,7 +653,7 @@ __device__ __forceinline__ void transform_tile(float *lds, Quads &q, int lane, i
 }
 
 template <int SCH>
-constexpr int lds_planes() { return SCH == SWELDENS ? 4 : 6; }
+constexpr int lds_planes() { return 2 * buf_planes<SCH>(); }
 
 template <int WAV, int SCH>
 __global__ __launch_bounds__(NTHREADS) void k_tile_forward(FwdArgs a, int ntx, int ntiles)
@@ -531,33 +807,51 @@ hipError_t inv(const InvArgs &a, hipStream_t s)
     return launch(k_tile_inverse<WAV, SCH>, dim3(g.blocks), dim3(NTHREADS), s, a, g.ntx, g.ntiles);
 }
 
+template <int WAV>
+hipError_t fwd_scheme(int scheme, const FwdArgs &a, hipStream_t s)
+{
+    switch (scheme) {
+    case MONO_STAR_TILE: return fwd<WAV, MONO_STAR_TILE>(a, s);
+    case SWELDENS: return fwd<WAV, SWELDENS>(a, s);
+    case IWAHASHI: return fwd<WAV, IWAHASHI>(a, s);
+    case MONOLITHIC: return fwd<WAV, MONOLITHIC>(a, s);
+    case EXPLOSIVE: return fwd<WAV, EXPLOSIVE>(a, s);
+    case EXPLOSIVE_STAR: return fwd<WAV, EXPLOSIVE_STAR>(a, s);
+    case IWAHASHI_STAR: return fwd<WAV, IWAHASHI_STAR>(a, s);
+    case POLYPHASE_STAR: return fwd<WAV, POLYPHASE_STAR>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int WAV>
+hipError_t inv_scheme(int scheme, const InvArgs &a, hipStream_t s)
+{
+    switch (scheme) {
+    case MONO_STAR_TILE: return inv<WAV, MONO_STAR_TILE>(a, s);
+    case SWELDENS: return inv<WAV, SWELDENS>(a, s);
+    case IWAHASHI: return inv<WAV, IWAHASHI>(a, s);
+    case MONOLITHIC: return inv<WAV, MONOLITHIC>(a, s);
+    case EXPLOSIVE: return inv<WAV, EXPLOSIVE>(a, s);
+    case EXPLOSIVE_STAR: return inv<WAV, EXPLOSIVE_STAR>(a, s);
+    case IWAHASHI_STAR: return inv<WAV, IWAHASHI_STAR>(a, s);
+    case POLYPHASE_STAR: return inv<WAV, POLYPHASE_STAR>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_tile_forward(int wavelet, int scheme, const FwdArgs &a, hipStream_t s)
 {
-    if (wavelet == CDF53) {
-        if (scheme == MONO_STAR_TILE) return fwd<CDF53, MONO_STAR_TILE>(a, s);
-        if (scheme == SWELDENS) return fwd<CDF53, SWELDENS>(a, s);
-        if (scheme == IWAHASHI) return fwd<CDF53, IWAHASHI>(a, s);
-    } else if (wavelet == CDF97) {
-        if (scheme == MONO_STAR_TILE) return fwd<CDF97, MONO_STAR_TILE>(a, s);
-        if (scheme == SWELDENS) return fwd<CDF97, SWELDENS>(a, s);
-        if (scheme == IWAHASHI) return fwd<CDF97, IWAHASHI>(a, s);
-    }
+    if (wavelet == CDF53) return fwd_scheme<CDF53>(scheme, a, s);
+    if (wavelet == CDF97) return fwd_scheme<CDF97>(scheme, a, s);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_tile_inverse(int wavelet, int scheme, const InvArgs &a, hipStream_t s)
 {
-    if (wavelet == CDF53) {
-        if (scheme == MONO_STAR_TILE) return inv<CDF53, MONO_STAR_TILE>(a, s);
-        if (scheme == SWELDENS) return inv<CDF53, SWELDENS>(a, s);
-        if (scheme == IWAHASHI) return inv<CDF53, IWAHASHI>(a, s);
-    } else if (wavelet == CDF97) {
-        if (scheme == MONO_STAR_TILE) return inv<CDF97, MONO_STAR_TILE>(a, s);
-        if (scheme == SWELDENS) return inv<CDF97, SWELDENS>(a, s);
-        if (scheme == IWAHASHI) return inv<CDF97, IWAHASHI>(a, s);
-    }
+    if (wavelet == CDF53) return inv_scheme<CDF53>(scheme, a, s);
+    if (wavelet == CDF97) return inv_scheme<CDF97>(scheme, a, s);
     return hipErrorInvalidValue;
 }
 

@@ -21,13 +21,17 @@ EXT_WHOLE_SYMMETRIC = 0
 NORM_UNIT_DC, NORM_PAPER = 0, 1
 SCHEME_AUTO, SCHEME_MONOLITHIC_STAR, SCHEME_SWELDENS, SCHEME_IWAHASHI, SCHEME_ROWCOL = 0, 1, 2, 3, 4
 SCHEME_MONOLITHIC_STAR_TILE = 5
+SCHEME_MONOLITHIC, SCHEME_EXPLOSIVE, SCHEME_EXPLOSIVE_STAR = 6, 7, 8
+SCHEME_IWAHASHI_STAR, SCHEME_POLYPHASE_STAR = 9, 10
 
 WAVELETS = {"cdf53": CDF53, "cdf97": CDF97, CDF53: CDF53, CDF97: CDF97}
 NORMS = {"unit_dc": NORM_UNIT_DC, "paper": NORM_PAPER, NORM_UNIT_DC: NORM_UNIT_DC,
          NORM_PAPER: NORM_PAPER}
 SCHEMES = {"auto": SCHEME_AUTO, "monolithic*": SCHEME_MONOLITHIC_STAR,
            "monolithic*-tile": SCHEME_MONOLITHIC_STAR_TILE, "sweldens": SCHEME_SWELDENS,
-           "iwahashi": SCHEME_IWAHASHI, "rowcol": SCHEME_ROWCOL}
+           "iwahashi": SCHEME_IWAHASHI, "rowcol": SCHEME_ROWCOL, "monolithic": SCHEME_MONOLITHIC,
+           "explosive": SCHEME_EXPLOSIVE, "explosive*": SCHEME_EXPLOSIVE_STAR,
+           "iwahashi*": SCHEME_IWAHASHI_STAR, "polyphase*": SCHEME_POLYPHASE_STAR}
 SCHEMES.update({v: v for v in list(SCHEMES.values())})
 
 EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_string",

@@ -117,14 +117,29 @@ def test_unsupported():
     o = dwt2.make_options()
     o.norm = 2
     assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
-    o = dwt2.make_options()
-    o.scheme = 6
-    assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
+    for bad in (11, -1, 1 << 20):  # one past the last scheme id, and garbage
+        o = dwt2.make_options()
+        o.scheme = bad
+        assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
     o = dwt2.make_options()
     o.arithmetic = 3
     assert _fwd(opt=o) == dwt2.E_UNSUPPORTED
-    for scheme in ("monolithic*-tile", "sweldens", "iwahashi", "rowcol"):
+    for scheme in ("monolithic*-tile", "sweldens", "iwahashi", "rowcol", "monolithic", "explosive",
+                   "explosive*", "iwahashi*", "polyphase*"):
         assert _fwd(opt=dwt2.make_options(scheme=scheme, arithmetic="fp64")) == dwt2.E_UNSUPPORTED
+
+
+def test_scheme_ids_match_header():
+    text = open(HEADER).read()
+    ids = dict(re.findall(r"DWT2_SCHEME_(\w+) = (\d+)", text))
+    names = {"AUTO": "auto", "MONOLITHIC_STAR": "monolithic*", "SWELDENS": "sweldens",
+             "IWAHASHI": "iwahashi", "ROWCOL": "rowcol", "MONOLITHIC_STAR_TILE": "monolithic*-tile",
+             "MONOLITHIC": "monolithic", "EXPLOSIVE": "explosive", "EXPLOSIVE_STAR": "explosive*",
+             "IWAHASHI_STAR": "iwahashi*", "POLYPHASE_STAR": "polyphase*"}
+    assert set(ids) == set(names)
+    for k, v in ids.items():
+        assert dwt2.SCHEMES[names[k]] == int(v), k
+    assert max(int(v) for v in ids.values()) == 10
 
 
 def test_workspace_and_alias_errors():

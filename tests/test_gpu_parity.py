@@ -22,7 +22,8 @@ pytestmark = pytest.mark.gpu
 
 from paper_1605_00561_amd import dwt2  # noqa: E402
 
-SCHEMES = ["monolithic*", "monolithic*-tile", "sweldens", "iwahashi", "rowcol"]
+SCHEMES = ["monolithic*", "monolithic*-tile", "sweldens", "iwahashi", "rowcol", "monolithic",
+           "explosive", "explosive*", "iwahashi*", "polyphase*"]
 WAVS = ["cdf53", "cdf97"]
 MAX_ABS, REL_L2 = 1e-3, 1e-6
 
