@@ -130,13 +130,20 @@ def test_alias_errors():
     assert both(a, n) == [dwt2.E_ALIAS] * 2
 
 
+# The fused kernel's tile: 64 x 24 quadruples including a halo of one
+# quadruple per side for 5/3.
+TILE_QW, TILE_QH = 64, 24
+
+
 def test_tile_total_overflow_is_an_argument_error():
-    # 2^19 x 2^19 is the largest accepted image (2^38 pixels); 51 of them hold
-    # more than 2^31 tiles in level 0, which a level launch cannot index.
+    # 2^19 x 2^19 is the largest accepted image (2^38 pixels); a few dozen of
+    # them hold more than 2^31 tiles in level 0, which a level launch cannot
+    # index.
     side = 2 ** 19
-    tiles = -(-(side // 2) // 62) * -(-(side // 2) // 26)
-    assert 50 * tiles < 2 ** 31 - 8 < 51 * tiles
-    for n, status in [(50, dwt2.OK), (51, dwt2.E_ARG)]:
+    tiles = -(-(side // 2) // (TILE_QW - 2)) * -(-(side // 2) // (TILE_QH - 2))
+    n_ok = (2 ** 31 - 8) // tiles
+    assert n_ok * tiles <= 2 ** 31 - 8 < (n_ok + 1) * tiles
+    for n, status in [(n_ok, dwt2.OK), (n_ok + 1, dwt2.E_ARG)]:
         a, _ = images(*[img("cdf53", 1, side, side)] * n)
         st, _ = dwt2.dwt2_batch_workspace_bytes(a, n, None)
         assert st == status
