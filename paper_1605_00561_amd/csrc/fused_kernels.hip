@@ -38,7 +38,7 @@ namespace {
 
 constexpr int TX = 64;  // quadruple columns per tile (one per lane)
 constexpr int NW = 4;   // wavefronts per work-group
-constexpr int RB = 6;   // quadruple rows per wavefront (tile row j * NW + w)
+constexpr int RB = 4;   // quadruple rows per wavefront (tile row j * NW + w)
 constexpr int TY = NW * RB;
 constexpr int NTHREADS = TX * NW;
 

@@ -130,9 +130,9 @@ def test_alias_errors():
     assert both(a, n) == [dwt2.E_ALIAS] * 2
 
 
-# The fused kernel's tile: 64 x 24 quadruples including a halo of one
+# The fused kernel's tile: 64 x 16 quadruples including a halo of one
 # quadruple per side for 5/3.
-TILE_QW, TILE_QH = 64, 24
+TILE_QW, TILE_QH = 64, 16
 
 
 def test_tile_total_overflow_is_an_argument_error():
