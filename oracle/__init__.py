@@ -22,9 +22,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dwt2_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle_dwt2.so")
 
-CDF53, CDF97 = 0, 1
+CDF53, CDF97, DD137 = 0, 1, 2
 NORM_UNIT_DC, NORM_PAPER = 0, 1
-WAVELETS = {"cdf53": CDF53, "cdf97": CDF97, CDF53: CDF53, CDF97: CDF97}
+WAVELETS = {"cdf53": CDF53, "cdf97": CDF97, "dd137": DD137, CDF53: CDF53, CDF97: CDF97,
+            DD137: DD137}
 NORMS = {"unit_dc": NORM_UNIT_DC, "paper": NORM_PAPER,
          NORM_UNIT_DC: NORM_UNIT_DC, NORM_PAPER: NORM_PAPER}
 

@@ -23,12 +23,16 @@
  * design notes of the repository):
  *   - Sample phase: L[n] = x[2n], H[n] = x[2n+1].  With this origin the
  *     paper's predict -1/2(1+z^-1) and update 1/4(1+z) (Sec. 5) read
- *     L[n], L[n+1] and H[n-1], H[n] respectively (an index relabelling of H).
+ *     L[n], L[n+1] and H[n-1], H[n] respectively (an index relabelling of H);
+ *     the DD 13/7 predict 1/16(z + z^-2) - 9/16(1 + z^-1) reads L[n-1..n+2]
+ *     and its update 9/32(1 + z) - 1/32(z^-1 + z^2) reads H[n-2..n+1].
  *   - Borders: whole-sample symmetric extension, period 2(N-1), applied to
  *     the neighbour index of every lifting step.
  *   - Odd lengths: L gets ceil(N/2) samples, H gets floor(N/2); N >= 2.
  *   - Normalisation: PAPER scales L by zeta and H by 1/zeta in each 1-D pass
- *     (Sec. 2 and Sec. 5).  UNIT_DC instead scales L by 1/g and H by g, where g
+ *     (Sec. 2 and Sec. 5); the paper gives no zeta for DD 13/7, which is
+ *     taken as sqrt(2), the value of the other interpolating transform (5/3),
+ *     whose unscaled low-pass also has DC gain 1.  UNIT_DC instead scales L by 1/g and H by g, where g
  *     is the DC gain of the unscaled low-pass, so a constant image keeps its
  *     value in LL.  The two differ per 2-D subband by exact powers of two.
  *   - Inverse (not treated by the paper): per level, columns then rows; undo
@@ -40,8 +44,8 @@
  * recursive in LL.
  *
  * No blocking, fusion or reordering of the arithmetic: each lifting step
- * updates every sample of one parity from the two nearest samples of the
- * other parity, which is order-free, so the loops below may visit lines and
+ * updates every sample of one parity from the nearest samples of the other
+ * parity (two for CDF, four for DD 13/7), which is order-free, so the loops below may visit lines and
  * samples in any order (chosen only for cache-friendly memory access).
  */
 #include <math.h>
@@ -60,15 +64,21 @@
 
 #define ORACLE_CDF53 0
 #define ORACLE_CDF97 1
+#define ORACLE_DD137 2
 
 #define ORACLE_NORM_UNIT_DC 0
 #define ORACLE_NORM_PAPER 1
 
+/*
+ * Each step is symmetric about the updated sample: in the interleaved signal
+ * y (y[2n] = L[n], y[2n+1] = H[n]) a predict or update step at position i adds
+ *   c1 (y[i-1] + y[i+1]) + c3 (y[i-3] + y[i+3]).
+ */
 typedef struct {
     int npairs;
-    double predict[2]; /* a_k of P^(k) = a_k (1 + z)    in the L=x[2n] phase */
-    double update[2];  /* b_k of U^(k) = b_k (1 + z^-1) in the L=x[2n] phase */
-    double zeta;       /* scaling factor of the paper's scaling step */
+    double predict[2], predict3[2]; /* c1, c3 of each predict step */
+    double update[2], update3[2];   /* c1, c3 of each update step */
+    double zeta;                    /* scaling factor of the paper's scaling step */
 } lifting_t;
 
 /*
@@ -87,6 +97,7 @@ typedef struct {
  */
 static int get_lifting(int wavelet, lifting_t *w)
 {
+    memset(w, 0, sizeof(*w));
     if (wavelet == ORACLE_CDF53) {
         w->npairs = 1;
         w->predict[0] = -0.5;
@@ -104,6 +115,17 @@ static int get_lifting(int wavelet, lifting_t *w)
         w->zeta = 1.14960439886024115979508;
         return ORACLE_OK;
     }
+    if (wavelet == ORACLE_DD137) {
+        /* Sec. 5: P(z) = 1/16 (z + z^-2) - 9/16 (1 + z^-1),
+         *         U(z) = 9/32 (1 + z) - 1/32 (z^-1 + z^2). */
+        w->npairs = 1;
+        w->predict[0] = -9.0 / 16.0;
+        w->predict3[0] = 1.0 / 16.0;
+        w->update[0] = 9.0 / 32.0;
+        w->update3[0] = -1.0 / 32.0;
+        w->zeta = sqrt(2.0);
+        return ORACLE_OK;
+    }
     return ORACLE_E_UNSUPPORTED;
 }
 
@@ -112,8 +134,8 @@ static double unscaled_dc_gain(const lifting_t *w)
 {
     double L = 1.0, H = 1.0;
     for (int k = 0; k < w->npairs; k++) {
-        H = H + w->predict[k] * (L + L);
-        L = L + w->update[k] * (H + H);
+        H = H + w->predict[k] * (L + L) + w->predict3[k] * (L + L);
+        L = L + w->update[k] * (H + H) + w->update3[k] * (H + H);
     }
     return L;
 }
@@ -149,20 +171,24 @@ static inline ptrdiff_t mirror(ptrdiff_t j, ptrdiff_t n)
 
 /*
  * One lifting step on `lines` lines of length n stored in `a`:
- *   y[i] += c * (y[m(i-1)] + y[m(i+1)])   for every i with i % 2 == parity.
+ *   y[i] += c1 (y[m(i-1)] + y[m(i+1)]) + c3 (y[m(i-3)] + y[m(i+3)])
+ * for every i with i % 2 == parity (the c3 term only when c3 != 0).
  * Samples of the updated parity read only samples of the other parity.
  * Rows (elem_stride == 1) loop lines outermost; columns (line_stride == 1)
  * loop sample positions outermost so that memory is walked row by row.
  */
 static void lift_step(double *a, ptrdiff_t lines, ptrdiff_t n, ptrdiff_t line_stride,
-                      ptrdiff_t elem_stride, int parity, double c)
+                      ptrdiff_t elem_stride, int parity, double c1, double c3)
 {
     if (elem_stride == 1) {
 #pragma omp parallel for schedule(static)
         for (ptrdiff_t j = 0; j < lines; j++) {
             double *y = a + j * line_stride;
-            for (ptrdiff_t i = parity; i < n; i += 2)
-                y[i] += c * (y[mirror(i - 1, n)] + y[mirror(i + 1, n)]);
+            for (ptrdiff_t i = parity; i < n; i += 2) {
+                double d = c1 * (y[mirror(i - 1, n)] + y[mirror(i + 1, n)]);
+                if (c3 != 0.0) d += c3 * (y[mirror(i - 3, n)] + y[mirror(i + 3, n)]);
+                y[i] += d;
+            }
         }
     } else {
 #pragma omp parallel for schedule(static)
@@ -170,8 +196,13 @@ static void lift_step(double *a, ptrdiff_t lines, ptrdiff_t n, ptrdiff_t line_st
             double *yi = a + i * elem_stride;
             const double *ym = a + mirror(i - 1, n) * elem_stride;
             const double *yp = a + mirror(i + 1, n) * elem_stride;
-            for (ptrdiff_t j = 0; j < lines; j++)
-                yi[j * line_stride] += c * (ym[j * line_stride] + yp[j * line_stride]);
+            const double *ym3 = a + mirror(i - 3, n) * elem_stride;
+            const double *yp3 = a + mirror(i + 3, n) * elem_stride;
+            for (ptrdiff_t j = 0; j < lines; j++) {
+                double d = c1 * (ym[j * line_stride] + yp[j * line_stride]);
+                if (c3 != 0.0) d += c3 * (ym3[j * line_stride] + yp3[j * line_stride]);
+                yi[j * line_stride] += d;
+            }
         }
     }
 }
@@ -228,8 +259,8 @@ static void lines_forward(const lifting_t *w, double s_lo, double s_hi, double *
                           ptrdiff_t elem_stride, double *tmp)
 {
     for (int k = 0; k < w->npairs; k++) {
-        lift_step(a, lines, n, line_stride, elem_stride, 1, w->predict[k]); /* predict: H from L */
-        lift_step(a, lines, n, line_stride, elem_stride, 0, w->update[k]);  /* update:  L from H */
+        lift_step(a, lines, n, line_stride, elem_stride, 1, w->predict[k], w->predict3[k]); /* H from L */
+        lift_step(a, lines, n, line_stride, elem_stride, 0, w->update[k], w->update3[k]);   /* L from H */
     }
     deinterleave(a, lines, n, line_stride, elem_stride, s_lo, s_hi, tmp);
 }
@@ -241,8 +272,8 @@ static void lines_inverse(const lifting_t *w, double s_lo, double s_hi, double *
 {
     interleave(a, lines, n, line_stride, elem_stride, s_lo, s_hi, tmp);
     for (int k = w->npairs - 1; k >= 0; k--) {
-        lift_step(a, lines, n, line_stride, elem_stride, 0, -w->update[k]);
-        lift_step(a, lines, n, line_stride, elem_stride, 1, -w->predict[k]);
+        lift_step(a, lines, n, line_stride, elem_stride, 0, -w->update[k], -w->update3[k]);
+        lift_step(a, lines, n, line_stride, elem_stride, 1, -w->predict[k], -w->predict3[k]);
     }
 }
 
@@ -283,7 +314,8 @@ int oracle_set_num_threads(int n)
 #endif
 }
 
-/* The lifting constants the oracle uses: coef = {a_0, b_0, a_1, b_1}. */
+/* The lifting constants the oracle uses: coef = {a_0, b_0, a_1, b_1}, the inner
+ * taps c1 of each predict and update (DD 13/7 also has outer taps c3). */
 int oracle_lifting_constants(int wavelet, int *npairs, double *coef, double *zeta)
 {
     lifting_t w;

@@ -13,8 +13,15 @@ lifting factorisation:
   synthesis low-pass sqrt(2) cos^4(w/2) (1 - y/y_r) modulated by (-1)^k,
   centred on x[2n+1].  These are in the paper's scale (DC gain sqrt(2)).
 
+* DD 13/7 ((4,4) Deslauriers-Dubuc): the 7-tap high-pass is x[2n+1] minus the
+  cubic Lagrange interpolation of x[2n-2], x[2n], x[2n+2], x[2n+4] at 2n+1,
+  with the weights computed here from the Lagrange formula; the 13-tap
+  low-pass adds to x[2n] the paper's update U(z) = 9/32 (1 + z) -
+  1/32 (z^-1 + z^2) (Sec. 5) of that high-pass, i.e. 9/32 (H[n-1] + H[n]) -
+  1/32 (H[n-2] + H[n+1]).  DC gain 1 (unit-DC scale).
+
 The paper's normalisation scales L by zeta and H by 1/zeta per axis, which
-for both wavelets gives a low-pass DC gain of sqrt(2); the unit-DC scale
+for every wavelet here gives a low-pass DC gain of sqrt(2); the unit-DC scale
 divides the low-pass by sqrt(2) and multiplies the high-pass by sqrt(2).
 """
 from __future__ import annotations
@@ -79,9 +86,34 @@ def cdf53_taps_unit_dc():
     return low, high
 
 
+def lagrange_weights(nodes, t):
+    """Weights of the Lagrange interpolation through `nodes`, evaluated at t."""
+    out = []
+    for i, a in enumerate(nodes):
+        w = 1.0
+        for j, b in enumerate(nodes):
+            if j != i:
+                w *= (t - b) / (a - b)
+        out.append(w)
+    return out
+
+
+def dd137_taps_unit_dc():
+    nodes = [-3, -1, 1, 3]  # even neighbours, relative to the odd sample
+    high = {0: 1.0}
+    for t, w in zip(nodes, lagrange_weights(nodes, 0.0)):
+        high[t] = -w
+    low = {0: 1.0}
+    for m, cu in ((-1, 9 / 32), (0, 9 / 32), (-2, -1 / 32), (1, -1 / 32)):
+        centre = 2 * m + 1  # H[n+m] sits at x[2(n+m)+1]
+        for k, v in high.items():
+            low[centre + k] = low.get(centre + k, 0.0) + cu * v
+    return low, high
+
+
 def analysis_taps(wavelet: str, norm: str):
-    if wavelet == "cdf53":
-        low, high = cdf53_taps_unit_dc()
+    if wavelet in ("cdf53", "dd137"):
+        low, high = cdf53_taps_unit_dc() if wavelet == "cdf53" else dd137_taps_unit_dc()
         if norm == "paper":
             low, high = _lscale(low, SQRT2), _lscale(high, 1 / SQRT2)
     elif wavelet == "cdf97":

@@ -4,7 +4,9 @@
   lifting factorisation (bruteforce.py), on every size 2..12 x 2..12 and on
   random sizes, one to three levels;
 * the CDF 9/7 lifting constants re-derived from the Daubechies polynomial;
-* the CDF 5/3 operators printed in Sec. 5;
+* the CDF 5/3 and DD 13/7 operators printed in Sec. 5;
+* DD 13/7: the high-pass annihilates cubics, the low-pass has no second
+  moment (the property its update was built for);
 * perfect reconstruction, linearity, constant / ramp / cubic images;
 * the exact power-of-two relation between the two normalisations;
 * error statuses.
@@ -17,7 +19,7 @@ import pytest
 import bruteforce as bf
 import oracle
 
-WAVS = ["cdf53", "cdf97"]
+WAVS = ["cdf53", "cdf97", "dd137"]
 NORMS = ["unit_dc", "paper"]
 
 
@@ -189,6 +191,55 @@ def test_cubic_cdf97(n):
     assert np.abs(HL[:, 1:kmax + 1]).max() < 1e-11
     assert np.abs(LH[1:kmax + 1, :]).max() < 1e-11
     assert np.abs(HH[1:kmax + 1, 1:kmax + 1]).max() < 1e-11
+
+
+def test_dd137_operators_as_printed():
+    """Sec. 5: P(z) = 1/16 (z + z^-2) - 9/16 (1 + z^-1), U(z) = 9/32 (1 + z) -
+    1/32 (z^-1 + z^2): in the L = x[2n] phase the predict adds -9/16 of L[n],
+    L[n+1] and 1/16 of L[n-1], L[n+2]; the update 9/32 of H[n-1], H[n] and
+    -1/32 of H[n-2], H[n+1].  Read back from 1-D impulse responses."""
+    n = 64
+    # H[k] response to a unit even sample x[2m] = L[m]: predict taps
+    x = np.zeros(n)
+    x[30] = 1.0  # L[15]
+    H = oracle.forward_1d(x, "dd137")[n // 2:]
+    np.testing.assert_allclose(H[12:18], [0, 1 / 16, -9 / 16, -9 / 16, 1 / 16, 0], rtol=0, atol=1e-15)
+    # L[k] response to a unit odd sample x[2m+1] = H[m] (which the predict
+    # leaves unchanged): update taps
+    x = np.zeros(n)
+    x[31] = 1.0  # H[15]
+    L = oracle.forward_1d(x, "dd137")[:n // 2]
+    np.testing.assert_allclose(L[12:20], [0, 0, -1 / 32, 9 / 32, 9 / 32, -1 / 32, 0, 0], rtol=0,
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [24, 33, 40])
+def test_dd137_highpass_annihilates_cubics(n):
+    """Deslauriers-Dubuc 4-point interpolation is exact for cubics, so H[k] = 0
+    wherever the 7-tap support [2k-2, 2k+4] lies inside the signal."""
+    t = np.arange(n, dtype=np.float64)
+    x = 2.0 + 0.7 * t - 0.05 * t ** 2 + 0.003 * t ** 3
+    H = oracle.forward_1d(x, "dd137")[(n + 1) // 2:]
+    kmax = (n - 5) // 2
+    assert np.abs(H[1:kmax + 1]).max() < 1e-10
+    assert abs(H[0]) > 1e-6
+
+
+def test_dd137_lowpass_moments():
+    """The low-pass impulse response (13 taps) sums to 1 and has zero first,
+    second and third moments about its centre."""
+    n = 64
+    ell = {}
+    for k in range(-8, 9):
+        x = np.zeros(n)
+        x[32 + k] = 1.0
+        ell[k] = oracle.forward_1d(x, "dd137")[16]  # L[16] sits at x[32]
+    support = [k for k, v in ell.items() if abs(v) > 1e-15]
+    assert min(support) == -6 and max(support) == 6
+    assert sum(ell.values()) == pytest.approx(1.0, abs=1e-15)
+    for m in (1, 2, 3):
+        assert abs(sum(v * k ** m for k, v in ell.items())) < 1e-13
+    assert abs(sum(v * k ** 4 for k, v in ell.items())) > 1.0
 
 
 @pytest.mark.parametrize("wav", WAVS)
