@@ -65,7 +65,9 @@ extern "C" {
 /* Wavelets (Sec. 5, "Evaluation"). */
 typedef enum dwt2_wavelet {
     DWT2_CDF53 = 0, /* P = -1/2 (1 + z^-1), U = 1/4 (1 + z): one lifting pair */
-    DWT2_CDF97 = 1  /* two lifting pairs alpha, beta, gamma, delta */
+    DWT2_CDF97 = 1, /* two lifting pairs alpha, beta, gamma, delta */
+    DWT2_DD137 = 2  /* (4,4) Deslauriers-Dubuc: P = 1/16 (z + z^-2) - 9/16 (1 + z^-1),
+                       U = 9/32 (1 + z) - 1/32 (z^-1 + z^2); MONOLITHIC_STAR only */
 } dwt2_wavelet;
 
 /* Boundary extension.  Only whole-sample symmetric is implemented. */
@@ -75,9 +77,9 @@ typedef enum dwt2_ext { DWT2_EXT_WHOLE_SYMMETRIC = 0 } dwt2_ext;
  * Normalisation, applied once per 2-D level to LL and HH (HL and LH have
  * scale 1 in both).  PAPER is the paper's scaling step diag(zeta, 1/zeta)
  * per axis (Sec. 2; zeta = sqrt(2) for 5/3, 1.14960439886... for 9/7):
- * LL * zeta^2, HH / zeta^2.  UNIT_DC scales so that a constant image keeps its
- * value in LL (5/3: no scaling; 9/7: LL / K^2, HH * K^2 with
- * K = 1.23017410491...).  Per level k the two differ by exact powers of two:
+ * LL * zeta^2, HH / zeta^2 (DD 13/7: the paper gives no zeta; sqrt(2) as for
+ * 5/3).  UNIT_DC scales so that a constant image keeps its value in LL (5/3
+ * and DD 13/7: no scaling; 9/7: LL / K^2, HH * K^2 with K = 1.23017410491...).  Per level k the two differ by exact powers of two:
  * PAPER = UNIT_DC * 2^(k-1) * {2 for LL, 1 for HL and LH, 1/2 for HH}.
  */
 typedef enum dwt2_norm { DWT2_NORM_UNIT_DC = 0, DWT2_NORM_PAPER = 1 } dwt2_norm;

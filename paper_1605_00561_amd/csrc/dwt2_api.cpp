@@ -33,7 +33,8 @@ struct Config {
 
 int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c)
 {
-    if (wavelet != DWT2_CDF53 && wavelet != DWT2_CDF97) return DWT2_E_UNSUPPORTED;
+    if (wavelet != DWT2_CDF53 && wavelet != DWT2_CDF97 && wavelet != DWT2_DD137)
+        return DWT2_E_UNSUPPORTED;
     if (ext != DWT2_EXT_WHOLE_SYMMETRIC) return DWT2_E_UNSUPPORTED;
     c->wavelet = wavelet;
     c->norm = DWT2_NORM_UNIT_DC;
@@ -55,6 +56,8 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     if (c->arithmetic == DWT2_ARITH_FP64 && c->scheme != DWT2_SCHEME_MONOLITHIC_STAR)
         return DWT2_E_UNSUPPORTED;
     if (c->arithmetic == DWT2_ARITH_AUTO) c->arithmetic = DWT2_ARITH_FP32;
+    // DD 13/7's four-tap operators are implemented by the fused kernel only.
+    if (c->wavelet == DWT2_DD137 && c->scheme != DWT2_SCHEME_MONOLITHIC_STAR) return DWT2_E_UNSUPPORTED;
     return DWT2_OK;
 }
 
@@ -104,8 +107,9 @@ Layout layout(int scheme, int levels, const int *ws, const int *hs)
 // Per-level scales of LL and HH.  The paper's scaling step diag(zeta, 1/zeta)
 // per axis gives LL * zeta^2 and HH / zeta^2 (HL, LH unscaled).  The unit-DC
 // normalisation divides LL by the squared DC gain K of the unscaled low-pass
-// (K = 1 for 5/3) and multiplies HH by K^2, so PAPER = UNIT_DC * {2, 1/2}
-// exactly, also after rounding to FP32.
+// (K = 1 for 5/3 and DD 13/7) and multiplies HH by K^2, so
+// PAPER = UNIT_DC * {2, 1/2} exactly, also after rounding to FP32 (zeta^2 K^2
+// = 2; the paper gives no zeta for DD 13/7, which takes sqrt(2) as 5/3 does).
 dwt2::Scale level_scale(int wavelet, int norm)
 {
     double K = 1.0;
@@ -456,17 +460,19 @@ int run_batch(bool inverse, const dwt2_image *images, int count, dwt2_ext ext,
     b.count = count;
     b.ll_gain = p.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
     const int norm = p.cfg.norm;
-    b.s[0] = inverse ? inverse_scale(DWT2_CDF53, norm) : level_scale(DWT2_CDF53, norm);
-    b.s[1] = inverse ? inverse_scale(DWT2_CDF97, norm) : level_scale(DWT2_CDF97, norm);
+    for (int wv = 0; wv < 3; wv++)
+        b.s[wv] = inverse ? inverse_scale(wv, norm) : level_scale(wv, norm);
     const bool fp64 = p.cfg.arithmetic == DWT2_ARITH_FP64;
+    bool has_dd = false;
+    for (int i = 0; i < count; i++) has_dd |= images[i].wavelet == DWT2_DD137;
     for (int j = 0; j < p.lmax; j++) {
         const int k = inverse ? p.lmax - 1 - j : j;
         b.level = k;
         b.start = (const int *)(wsb + p.tab_off) + (size_t)k * (count + 1);
         b.ntiles = p.start[(size_t)k * (count + 1) + count];
         b.quantum = norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
-        e = inverse ? dwt2::launch_batch_inverse(fp64, b, stream)
-                    : dwt2::launch_batch_forward(fp64, b, stream);
+        e = inverse ? dwt2::launch_batch_inverse(fp64, has_dd, b, stream)
+                    : dwt2::launch_batch_forward(fp64, has_dd, b, stream);
         if (e != hipSuccess) return hip_status(e);
     }
     return DWT2_OK;

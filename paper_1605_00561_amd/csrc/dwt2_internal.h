@@ -7,7 +7,7 @@
 
 namespace dwt2 {
 
-enum Wavelet : int { CDF53 = 0, CDF97 = 1 };
+enum Wavelet : int { CDF53 = 0, CDF97 = 1, DD137 = 2 };
 // Scheme ids as in dwt2.h; MONO_STAR is the fused register-blocked kernel,
 // ROWCOL the two-pass kernels, all others run in the LDS tile harness.
 enum Scheme : int {
@@ -47,6 +47,18 @@ struct Lift<CDF97> {
     {
         return k == 0 ? -0.0529801185729614146241296f : 0.443506852043971152115604f;
     }
+};
+
+// DD 13/7 (Sec. 5): P(z) = 1/16 (z + z^-2) - 9/16 (1 + z^-1) and
+// U(z) = 9/32 (1 + z) - 1/32 (z^-1 + z^2).  In the L = x[2n] phase the
+// predict reads L[n-1..n+2] and the update H[n-2..n+1]; p and u are the
+// scalar parts P0, U0 (the taps at n).  The neighbour taps are listed where
+// the kernels use them.
+template <>
+struct Lift<DD137> {
+    static constexpr int K = 1;
+    __host__ __device__ static constexpr float p(int) { return -0.5625f; }
+    __host__ __device__ static constexpr float u(int) { return 0.28125f; }
 };
 
 // Per-level scale of LL and HH (HL and LH are unscaled in both normalisations).
@@ -141,7 +153,7 @@ struct BatchLevel {
     const BatchImage *imgs;
     const int *start;
     int count, ntiles, level;
-    Scale s[2];     // per wavelet: forward scales, or reciprocals for the inverse
+    Scale s[3];     // per wavelet: forward scales, or reciprocals for the inverse
     float ll_gain;
     float quantum;
 };
@@ -152,8 +164,9 @@ size_t batch_table_bytes(int count, int lmax);
 
 // Tiles of the fused kernel for one W x H level (0 when a side is below 2).
 long long fused_tile_count(int wavelet, int W, int H);
-hipError_t launch_batch_forward(bool fp64, const BatchLevel &b, hipStream_t s);
-hipError_t launch_batch_inverse(bool fp64, const BatchLevel &b, hipStream_t s);
+// has_dd: the batch holds a DD 13/7 image (its taller tile needs more LDS).
+hipError_t launch_batch_forward(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s);
+hipError_t launch_batch_inverse(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s);
 // Copy `bytes` (a multiple of 4) from host memory to device memory `dst` with
 // kernels whose arguments carry the data: stream-ordered and capturable, and
 // the host buffer may be reused as soon as the call returns.

@@ -37,10 +37,34 @@ namespace dwt2 {
 namespace {
 
 constexpr int TX = 64;  // quadruple columns per tile (one per lane)
-constexpr int NW = 4;   // wavefronts per work-group
-constexpr int RB = 4;   // quadruple rows per wavefront (tile row j * NW + w)
-constexpr int TY = NW * RB;
+constexpr int NW = 4;   // wavefronts per work-group (tile row j * NW + w)
 constexpr int NTHREADS = TX * NW;
+
+// Tile shape per wavelet: RB quadruple rows per wavefront, HQ quadruples of
+// halo per side (how far one level's lifting pairs reach: 1 per pair for the
+// two-tap CDF operators, 3 for DD 13/7's four-tap pair), PAD padding rows of
+// the LDS planes (the operators' vertical reach).
+template <int WAV>
+struct Shape;
+template <>
+struct Shape<CDF53> {
+    static constexpr int RB = 4, HQ = 1, PAD = 1;
+};
+template <>
+struct Shape<CDF97> {
+    static constexpr int RB = 4, HQ = 2, PAD = 1;
+};
+template <>
+struct Shape<DD137> {
+    static constexpr int RB = 6, HQ = 3, PAD = 2;
+};
+template <int WAV>
+constexpr int tile_h() { return NW * Shape<WAV>::RB; }
+template <int WAV>
+constexpr int plane_rows() { return tile_h<WAV>() + 2 * Shape<WAV>::PAD; }
+// Elements of the two plane buffers (two components each) a tile needs.
+template <int WAV>
+constexpr int plane_elems() { return 2 * 2 * plane_rows<WAV>() * TX; }
 
 enum { LL = 0, HL = 1, LH = 2, HH = 3 };
 
@@ -91,168 +115,35 @@ __device__ __forceinline__ int xcd_tile(int ntiles)
     return t < ntiles ? t : -1;
 }
 
-// Row planes: [buffer][component][tile row + 1][lane]; rows -1 and TY are
-// padding that only halo rows read.
-template <typename T>
+// Row planes in LDS: [buffer][component][tile row + PAD][lane]; the PAD rows
+// above and below the tile are read only by halo rows.
+template <int WAV, typename T>
 struct Planes {
-    T v[2][2][TY + 2][TX];
+    T *base;
+    __device__ __forceinline__ T &at(int b, int comp, int r, int c) const
+    {
+        return base[((b * 2 + comp) * plane_rows<WAV>() + r + Shape<WAV>::PAD) * TX + c];
+    }
 };
-
-template <typename T>
-__device__ __forceinline__ T &plane(Planes<T> &s, int b, int comp, int r, int c)
-{
-    return s.v[b][comp][r + 1][c];
-}
 
 __device__ __forceinline__ constexpr int tile_row(int j, int w) { return j * NW + w; }
 
-// T_{P1} on one quadruple: the neighbour part of the spatial predict, from
-// pre-step neighbour values (right LL, LH; lower LL, HL; lower-right LL).
-template <typename T>
-__device__ __forceinline__ void predict_q(T (&q)[4], T llr, T lld, T lldr, T hld, T lhr, T p, T p2)
+// Value of lane (own + d) for d in {-2, -1, 1, 2} by DPP wave shifts; lanes
+// past either end get 0 (they hold halo columns).
+template <int D, typename T>
+__device__ __forceinline__ T lane_shift(T v)
 {
-    q[HL] = mad(p, llr, q[HL]);
-    q[LH] = mad(p, lld, q[LH]);
-    q[HH] = mad(p2, lldr, mad(p, hld, mad(p, lhr, q[HH])));
+    if constexpr (D == 1) return from_right(v);
+    else if constexpr (D == -1) return from_left(v);
+    else if constexpr (D == 2) return from_right(from_right(v));
+    else return from_left(from_left(v));
 }
 
-// S_{U1} on one quadruple: the neighbour part of the spatial update, from
-// pre-step neighbour values (left HL, HH; upper LH, HH; upper-left HH).
-template <typename T>
-__device__ __forceinline__ void update_q(T (&q)[4], T hll, T lhu, T hhul, T hhu, T hhl, T u, T u2)
-{
-    q[LL] = mad(u, hll, mad(u, lhu, mad(u2, hhul, q[LL])));
-    q[HL] = mad(u, hhu, q[HL]);
-    q[LH] = mad(u, hhl, q[LH]);
-}
-
-// T_{-P1} on one quadruple.
-template <typename T>
-__device__ __forceinline__ void unpredict_q(T (&q)[4], T llr, T lld, T lldr, T hld, T lhr, T p, T p2)
-{
-    q[HL] = mad(-p, llr, q[HL]);
-    q[LH] = mad(-p, lld, q[LH]);
-    q[HH] = mad(p2, lldr, mad(-p, hld, mad(-p, lhr, q[HH])));
-}
-
-// S_{-U1} on one quadruple.
-template <typename T>
-__device__ __forceinline__ void unupdate_q(T (&q)[4], T hll, T lhu, T hhul, T hhu, T hhl, T u, T u2)
-{
-    q[LL] = mad(-u, hll, mad(-u, lhu, mad(u2, hhul, q[LL])));
-    q[HL] = mad(-u, hhu, q[HL]);
-    q[LH] = mad(-u, hhl, q[LH]);
-}
-
-// Neighbour part of a predict step: the row below comes from plane buffer b
-// (published before the barrier), the right neighbours by DPP.
-template <bool INV, typename T>
-__device__ __forceinline__ void predict_step(T (&q)[RB][4], Planes<T> &sm, int b, int w, int lane, T p)
-{
-    const T p2 = p * p;
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-        const int r = tile_row(j, w);
-        const T lld = plane(sm, b, 0, r + 1, lane);
-        const T hld = plane(sm, b, 1, r + 1, lane);
-        const T lldr = from_right(lld);
-        const T llr = from_right(q[j][LL]);
-        const T lhr = from_right(q[j][LH]);
-        if (!INV)
-            predict_q(q[j], llr, lld, lldr, hld, lhr, p, p2);
-        else
-            unpredict_q(q[j], llr, lld, lldr, hld, lhr, p, p2);
-    }
-}
-
-// Neighbour part of an update step: the row above from plane buffer b, the
-// left neighbours by DPP.
-template <bool INV, typename T>
-__device__ __forceinline__ void update_step(T (&q)[RB][4], Planes<T> &sm, int b, int w, int lane, T u)
-{
-    const T u2 = u * u;
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-        const int r = tile_row(j, w);
-        const T lhu = plane(sm, b, 0, r - 1, lane);
-        const T hhu = plane(sm, b, 1, r - 1, lane);
-        const T hhul = from_left(hhu);
-        const T hll = from_left(q[j][HL]);
-        const T hhl = from_left(q[j][HH]);
-        if (!INV)
-            update_q(q[j], hll, lhu, hhul, hhu, hhl, u, u2);
-        else
-            unupdate_q(q[j], hll, lhu, hhul, hhu, hhl, u, u2);
-    }
-}
-
-// The components a step reads across rows: LL, HL for the predict (buffer
-// 0), LH, HH for the update (buffer 1).
-template <typename T>
-__device__ __forceinline__ void publish_predict(T (&q)[RB][4], Planes<T> &sm, int w, int lane)
-{
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-        plane(sm, 0, 0, tile_row(j, w), lane) = q[j][LL];
-        plane(sm, 0, 1, tile_row(j, w), lane) = q[j][HL];
-    }
-}
-template <typename T>
-__device__ __forceinline__ void publish_update(T (&q)[RB][4], Planes<T> &sm, int w, int lane)
-{
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-        plane(sm, 1, 0, tile_row(j, w), lane) = q[j][LH];
-        plane(sm, 1, 1, tile_row(j, w), lane) = q[j][HH];
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void scalar_predict(T (&q)[RB][4], T p)
-{
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-        q[j][HL] = mad(p, q[j][LL], q[j][HL]);  // T^H_{P0}
-        q[j][HH] = mad(p, q[j][LH], q[j][HH]);
-        q[j][LH] = mad(p, q[j][LL], q[j][LH]);  // T^V_{P0}
-        q[j][HH] = mad(p, q[j][HL], q[j][HH]);
-    }
-}
-template <typename T>
-__device__ __forceinline__ void scalar_update(T (&q)[RB][4], T u)
-{
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-        q[j][LL] = mad(u, q[j][HL], q[j][LL]);  // S^H_{U0}
-        q[j][LH] = mad(u, q[j][HH], q[j][LH]);
-        q[j][LL] = mad(u, q[j][LH], q[j][LL]);  // S^V_{U0}
-        q[j][HL] = mad(u, q[j][HH], q[j][HL]);
-    }
-}
-template <typename T>
-__device__ __forceinline__ void scalar_unupdate(T (&q)[RB][4], T u)
-{
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-        q[j][LL] = mad(-u, q[j][LH], q[j][LL]);  // undo S^V_{U0}
-        q[j][HL] = mad(-u, q[j][HH], q[j][HL]);
-        q[j][LL] = mad(-u, q[j][HL], q[j][LL]);  // undo S^H_{U0}
-        q[j][LH] = mad(-u, q[j][HH], q[j][LH]);
-    }
-}
-template <typename T>
-__device__ __forceinline__ void scalar_unpredict(T (&q)[RB][4], T p)
-{
-#pragma unroll
-    for (int j = 0; j < RB; j++) {
-        q[j][HH] = mad(-p, q[j][HL], q[j][HH]);  // undo T^V_{P0}
-        q[j][LH] = mad(-p, q[j][LL], q[j][LH]);
-        q[j][HH] = mad(-p, q[j][LH], q[j][HH]);  // undo T^H_{P0}
-        q[j][HL] = mad(-p, q[j][LL], q[j][HL]);
-    }
-}
-
-// Lifting constants in the arithmetic type: FP32 literals, or for FP64 the
+// Neighbour parts of the lifting operators, P1 = P - P0 and U1 = U - U0, as
+// taps (offset in quadruples, coefficient) in the L = x[2n] phase:
+//   CDF:     P1 = {+1: p}, U1 = {-1: u}            (pair k's p, u)
+//   DD 13/7: P1 = {+1: -9/16, -1: 1/16, +2: 1/16}, U1 = {-1: 9/32, +1: -1/32, -2: -1/32}.
+// Lifting constants are in the arithmetic type: FP32 literals, or for FP64 the
 // same values written to double precision.
 template <int WAV, typename T>
 struct Coef {
@@ -265,38 +156,192 @@ struct Coef<CDF97, double> {
     __device__ static double u(int k) { return k == 0 ? -0.0529801185729614146241296 : 0.443506852043971152115604; }
 };
 
+// acc + sum_i tap_i * f(offset_i) over the predict (P1) or update (U1) taps.
+template <int WAV, bool PRED, typename T, typename F>
+__device__ __forceinline__ T taps(T acc, int k, F f)
+{
+    if constexpr (WAV == DD137) {
+        if constexpr (PRED)
+            return mad((T)0.0625, f.template get<2>(), mad((T)0.0625, f.template get<-1>(),
+                       mad((T)-0.5625, f.template get<1>(), acc)));
+        else
+            return mad((T)-0.03125, f.template get<-2>(), mad((T)-0.03125, f.template get<1>(),
+                       mad((T)0.28125, f.template get<-1>(), acc)));
+    } else {
+        if constexpr (PRED) return mad(Coef<WAV, T>::p(k), f.template get<1>(), acc);
+        else return mad(Coef<WAV, T>::u(k), f.template get<-1>(), acc);
+    }
+}
+
+// Accessors for taps(): a value of this lane's row shifted across lanes, or a
+// row of a plane above / below this row.
+template <typename T>
+struct Across {
+    T v;
+    template <int D>
+    __device__ __forceinline__ T get() const { return lane_shift<D>(v); }
+};
 template <int WAV, typename T>
-__device__ __forceinline__ void forward_tile(T (&q)[RB][4], Planes<T> &sm, int w, int lane)
+struct Down {
+    const Planes<WAV, T> &pl;
+    int b, comp, r, lane;
+    template <int D>
+    __device__ __forceinline__ T get() const { return pl.at(b, comp, r + D, lane); }
+};
+
+// Neighbour part of a predict step, T_{P1} (inverse: T_{-P1}), on every row:
+//   HL += P1 LL;  LH += P1* LL;  HH += P1 P1* LL + P1* HL + P1 LH
+// with P1 horizontal (across lanes, by DPP) and P1* vertical (rows of plane
+// buffer 0, published before the barrier); P1 P1* LL is P1 applied to the
+// vertical sum.  All reads are of pre-step values.  The inverse reads the
+// post-step values and subtracts, except the P1 P1* term, which keeps its sign.
+template <int WAV, bool INV, int RB, typename T>
+__device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane, int k)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        const int r = tile_row(j, w);
+        const T vll = taps<WAV, true>((T)0, k, Down<WAV, T>{pl, 0, 0, r, lane});
+        const T vhl = taps<WAV, true>((T)0, k, Down<WAV, T>{pl, 0, 1, r, lane});
+        const T hll = taps<WAV, true>((T)0, k, Across<T>{q[j][LL]});
+        const T hlh = taps<WAV, true>((T)0, k, Across<T>{q[j][LH]});
+        const T dll = taps<WAV, true>((T)0, k, Across<T>{vll});
+        if (!INV) {
+            q[j][HL] += hll;
+            q[j][LH] += vll;
+            q[j][HH] += dll + (vhl + hlh);
+        } else {
+            q[j][HL] -= hll;
+            q[j][LH] -= vll;
+            q[j][HH] += dll - (vhl + hlh);
+        }
+    }
+}
+
+// Neighbour part of an update step, S_{U1} (inverse: S_{-U1}), on every row:
+//   LL += U1 HL + U1* LH + U1 U1* HH;  HL += U1* HH;  LH += U1 HH
+// with the rows of plane buffer 1.
+template <int WAV, bool INV, int RB, typename T>
+__device__ __forceinline__ void update_step(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane, int k)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        const int r = tile_row(j, w);
+        const T vlh = taps<WAV, false>((T)0, k, Down<WAV, T>{pl, 1, 0, r, lane});
+        const T vhh = taps<WAV, false>((T)0, k, Down<WAV, T>{pl, 1, 1, r, lane});
+        const T hhl = taps<WAV, false>((T)0, k, Across<T>{q[j][HL]});
+        const T hhh = taps<WAV, false>((T)0, k, Across<T>{q[j][HH]});
+        const T dhh = taps<WAV, false>((T)0, k, Across<T>{vhh});
+        if (!INV) {
+            q[j][LL] += dhh + (hhl + vlh);
+            q[j][HL] += vhh;
+            q[j][LH] += hhh;
+        } else {
+            q[j][LL] += dhh - (hhl + vlh);
+            q[j][HL] -= vhh;
+            q[j][LH] -= hhh;
+        }
+    }
+}
+
+// The components a step reads across rows: LL, HL for the predict (buffer
+// 0), LH, HH for the update (buffer 1).
+template <int WAV, int RB, typename T>
+__device__ __forceinline__ void publish_predict(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        pl.at(0, 0, tile_row(j, w), lane) = q[j][LL];
+        pl.at(0, 1, tile_row(j, w), lane) = q[j][HL];
+    }
+}
+template <int WAV, int RB, typename T>
+__device__ __forceinline__ void publish_update(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        pl.at(1, 0, tile_row(j, w), lane) = q[j][LH];
+        pl.at(1, 1, tile_row(j, w), lane) = q[j][HH];
+    }
+}
+
+template <int RB, typename T>
+__device__ __forceinline__ void scalar_predict(T (&q)[RB][4], T p)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        q[j][HL] = mad(p, q[j][LL], q[j][HL]);  // T^H_{P0}
+        q[j][HH] = mad(p, q[j][LH], q[j][HH]);
+        q[j][LH] = mad(p, q[j][LL], q[j][LH]);  // T^V_{P0}
+        q[j][HH] = mad(p, q[j][HL], q[j][HH]);
+    }
+}
+template <int RB, typename T>
+__device__ __forceinline__ void scalar_update(T (&q)[RB][4], T u)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        q[j][LL] = mad(u, q[j][HL], q[j][LL]);  // S^H_{U0}
+        q[j][LH] = mad(u, q[j][HH], q[j][LH]);
+        q[j][LL] = mad(u, q[j][LH], q[j][LL]);  // S^V_{U0}
+        q[j][HL] = mad(u, q[j][HH], q[j][HL]);
+    }
+}
+template <int RB, typename T>
+__device__ __forceinline__ void scalar_unupdate(T (&q)[RB][4], T u)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        q[j][LL] = mad(-u, q[j][LH], q[j][LL]);  // undo S^V_{U0}
+        q[j][HL] = mad(-u, q[j][HH], q[j][HL]);
+        q[j][LL] = mad(-u, q[j][HL], q[j][LL]);  // undo S^H_{U0}
+        q[j][LH] = mad(-u, q[j][HH], q[j][LH]);
+    }
+}
+template <int RB, typename T>
+__device__ __forceinline__ void scalar_unpredict(T (&q)[RB][4], T p)
+{
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        q[j][HH] = mad(-p, q[j][HL], q[j][HH]);  // undo T^V_{P0}
+        q[j][LH] = mad(-p, q[j][LL], q[j][LH]);
+        q[j][HH] = mad(-p, q[j][LH], q[j][HH]);  // undo T^H_{P0}
+        q[j][HL] = mad(-p, q[j][LL], q[j][HL]);
+    }
+}
+
+template <int WAV, int RB, typename T>
+__device__ __forceinline__ void forward_tile(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane)
 {
     using C = Coef<WAV, T>;
 #pragma unroll
     for (int k = 0; k < Lift<WAV>::K; k++) {
-        publish_predict(q, sm, w, lane);
+        publish_predict(q, pl, w, lane);
         __syncthreads();
-        predict_step<false>(q, sm, 0, w, lane, C::p(k));
+        predict_step<WAV, false>(q, pl, w, lane, k);
         scalar_predict(q, C::p(k));
-        publish_update(q, sm, w, lane);
+        publish_update(q, pl, w, lane);
         __syncthreads();
-        update_step<false>(q, sm, 1, w, lane, C::u(k));
+        update_step<WAV, false>(q, pl, w, lane, k);
         scalar_update(q, C::u(k));
     }
 }
 
-template <int WAV, typename T>
-__device__ __forceinline__ void inverse_tile(T (&q)[RB][4], Planes<T> &sm, int w, int lane)
+template <int WAV, int RB, typename T>
+__device__ __forceinline__ void inverse_tile(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane)
 {
     using C = Coef<WAV, T>;
 #pragma unroll
     for (int kk = 0; kk < Lift<WAV>::K; kk++) {
         const int k = Lift<WAV>::K - 1 - kk;
         scalar_unupdate(q, C::u(k));
-        publish_update(q, sm, w, lane);
+        publish_update(q, pl, w, lane);
         __syncthreads();
-        update_step<true>(q, sm, 1, w, lane, C::u(k));
+        update_step<WAV, true>(q, pl, w, lane, k);
         scalar_unpredict(q, C::p(k));
-        publish_predict(q, sm, w, lane);
+        publish_predict(q, pl, w, lane);
         __syncthreads();
-        predict_step<true>(q, sm, 0, w, lane, C::p(k));
+        predict_step<WAV, true>(q, pl, w, lane, k);
     }
 }
 
@@ -308,10 +353,11 @@ __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)
 // Horizontal fast path: the tile's 128 pixel columns lie inside the image and
 // rows are 8-byte aligned, so each pixel-row pair is one float2 per lane.
 template <int WAV, typename T, bool VEC>
-__device__ __forceinline__ void fwd_body(const FwdArgs &a, Planes<T> &sm, int tc, int tr, int w, int lane)
+__device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int tr, int w, int lane)
 {
-    constexpr int HQ = Lift<WAV>::K;
+    constexpr int HQ = Shape<WAV>::HQ, RB = Shape<WAV>::RB, TY = tile_h<WAV>();
     constexpr int IX = TX - 2 * HQ, IY = TY - 2 * HQ;
+    const Planes<WAV, T> pl{lds};
     const int W = a.W, H = a.H;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1, WH = W >> 1, HHr = H >> 1;
     const int qc = tc * IX - HQ + lane;
@@ -345,7 +391,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, Planes<T> &sm, int tc
 #pragma unroll
         for (int e = 0; e < 4; e++) q[j][e] = (T)raw[j][e] - (T)c;
 
-    forward_tile<WAV>(q, sm, w, lane);
+    forward_tile(q, pl, w, lane);
 
     if (lane < HQ || lane >= TX - HQ || qc >= QW) return;
     const float cll = c * a.ll_gain;
@@ -366,10 +412,11 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, Planes<T> &sm, int tc
 }
 
 template <int WAV, typename T, bool VEC>
-__device__ __forceinline__ void inv_body(const InvArgs &a, Planes<T> &sm, int tc, int tr, int w, int lane)
+__device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int tr, int w, int lane)
 {
-    constexpr int HQ = Lift<WAV>::K;
+    constexpr int HQ = Shape<WAV>::HQ, RB = Shape<WAV>::RB, TY = tile_h<WAV>();
     constexpr int IX = TX - 2 * HQ, IY = TY - 2 * HQ;
+    const Planes<WAV, T> pl{lds};
     const int W = a.W, H = a.H;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1;
     const int qc = tc * IX - HQ + lane;
@@ -397,7 +444,7 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, Planes<T> &sm, int tc
         q[j][HH] = (T)hrow[QW + ch] * (T)a.inv_s.hh;
     }
 
-    inverse_tile<WAV>(q, sm, w, lane);
+    inverse_tile(q, pl, w, lane);
 
     if (lane < HQ || lane >= TX - HQ || qc >= QW) return;
     const int px = 2 * qc;
@@ -426,8 +473,8 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, Planes<T> &sm, int tc
 template <int WAV, typename T>
 __global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, int ntiles)
 {
-    constexpr int HQ = Lift<WAV>::K;
-    __shared__ Planes<T> sm;
+    constexpr int HQ = Shape<WAV>::HQ;
+    __shared__ T sm[plane_elems<WAV>()];
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;  // uniform over the work-group
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
@@ -444,8 +491,8 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, 
 template <int WAV, typename T>
 __global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, int ntiles)
 {
-    constexpr int HQ = Lift<WAV>::K;
-    __shared__ Planes<T> sm;
+    constexpr int HQ = Shape<WAV>::HQ;
+    __shared__ T sm[plane_elems<WAV>()];
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
@@ -484,10 +531,44 @@ __device__ __forceinline__ int level_size(int n, int k)
     return (int)(((long long)n + (1LL << k) - 1) >> k);
 }
 
-template <typename T>
+// One tile of image level `a`, given the tile's index within the image.
+template <int WAV, typename T>
+__device__ __forceinline__ void batch_fwd_tile(const FwdArgs &a, T *lds, int local, int w, int lane)
+{
+    constexpr int HQ = Shape<WAV>::HQ;
+    const int ntx = ((a.W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
+    const int tc = local % ntx, tr = local / ntx;
+    const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+    const bool aligned = (((uintptr_t)a.in | (uintptr_t)(a.in_pitch * 4)) & 7) == 0;
+    if (aligned && px_first >= 0 && px_first + 2 * TX <= a.W)
+        fwd_body<WAV, T, true>(a, lds, tc, tr, w, lane);
+    else
+        fwd_body<WAV, T, false>(a, lds, tc, tr, w, lane);
+}
+template <int WAV, typename T>
+__device__ __forceinline__ void batch_inv_tile(const InvArgs &a, T *lds, int local, int w, int lane)
+{
+    constexpr int HQ = Shape<WAV>::HQ;
+    const int ntx = ((a.W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
+    const int tc = local % ntx, tr = local / ntx;
+    const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+    const bool aligned = (((uintptr_t)a.out | (uintptr_t)(a.out_pitch * 4)) & 7) == 0;
+    if (aligned && px_first >= 0 && px_first + 2 * TX <= a.W)
+        inv_body<WAV, T, true>(a, lds, tc, tr, w, lane);
+    else
+        inv_body<WAV, T, false>(a, lds, tc, tr, w, lane);
+}
+
+// LDS of a batched launch: the largest plane set of the wavelets it may meet
+// (DD 13/7's taller tile only when the batch holds such an image).
+static_assert(plane_elems<CDF53>() == plane_elems<CDF97>(), "CDF tiles share one plane size");
+template <bool DD>
+constexpr int batch_plane_elems() { return DD ? plane_elems<DD137>() : plane_elems<CDF97>(); }
+
+template <typename T, bool DD>
 __global__ __launch_bounds__(NTHREADS) void k_batch_forward(BatchLevel b)
 {
-    __shared__ Planes<T> sm;
+    __shared__ T sm[batch_plane_elems<DD>()];
     const int t = xcd_tile(b.ntiles);
     if (t < 0) return;
     const int i = find_image(b.start, b.count, t);
@@ -503,37 +584,20 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_forward(BatchLevel b)
     a.det_pitch = im.dst_pitch;
     a.W = W;
     a.H = H;
-    a.s = b.s[im.wavelet == CDF97];
+    a.s = b.s[im.wavelet];
     a.ll_gain = b.ll_gain;
     a.quantum = b.quantum;
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
     const int local = t - b.start[i];
-    const bool aligned = (((uintptr_t)a.in | (uintptr_t)(a.in_pitch * 4)) & 7) == 0;
-    if (im.wavelet == CDF97) {
-        constexpr int HQ = Lift<CDF97>::K;
-        const int ntx = ((W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
-        const int tc = local % ntx, tr = local / ntx;
-        const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
-        if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
-            fwd_body<CDF97, T, true>(a, sm, tc, tr, w, lane);
-        else
-            fwd_body<CDF97, T, false>(a, sm, tc, tr, w, lane);
-    } else {
-        constexpr int HQ = Lift<CDF53>::K;
-        const int ntx = ((W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
-        const int tc = local % ntx, tr = local / ntx;
-        const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
-        if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
-            fwd_body<CDF53, T, true>(a, sm, tc, tr, w, lane);
-        else
-            fwd_body<CDF53, T, false>(a, sm, tc, tr, w, lane);
-    }
+    if (im.wavelet == CDF97) batch_fwd_tile<CDF97>(a, sm, local, w, lane);
+    else if (DD && im.wavelet == DD137) batch_fwd_tile<DD ? DD137 : CDF53>(a, sm, local, w, lane);
+    else batch_fwd_tile<CDF53>(a, sm, local, w, lane);
 }
 
-template <typename T>
+template <typename T, bool DD>
 __global__ __launch_bounds__(NTHREADS) void k_batch_inverse(BatchLevel b)
 {
-    __shared__ Planes<T> sm;
+    __shared__ T sm[batch_plane_elems<DD>()];
     const int t = xcd_tile(b.ntiles);
     if (t < 0) return;
     const int i = find_image(b.start, b.count, t);
@@ -549,31 +613,14 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_inverse(BatchLevel b)
     a.out_pitch = k == 0 ? im.dst_pitch : (ptrdiff_t)W;
     a.W = W;
     a.H = H;
-    a.inv_s = b.s[im.wavelet == CDF97];
+    a.inv_s = b.s[im.wavelet];
     a.ll_gain = b.ll_gain;
     a.quantum = b.quantum;
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
     const int local = t - b.start[i];
-    const bool aligned = (((uintptr_t)a.out | (uintptr_t)(a.out_pitch * 4)) & 7) == 0;
-    if (im.wavelet == CDF97) {
-        constexpr int HQ = Lift<CDF97>::K;
-        const int ntx = ((W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
-        const int tc = local % ntx, tr = local / ntx;
-        const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
-        if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
-            inv_body<CDF97, T, true>(a, sm, tc, tr, w, lane);
-        else
-            inv_body<CDF97, T, false>(a, sm, tc, tr, w, lane);
-    } else {
-        constexpr int HQ = Lift<CDF53>::K;
-        const int ntx = ((W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
-        const int tc = local % ntx, tr = local / ntx;
-        const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
-        if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
-            inv_body<CDF53, T, true>(a, sm, tc, tr, w, lane);
-        else
-            inv_body<CDF53, T, false>(a, sm, tc, tr, w, lane);
-    }
+    if (im.wavelet == CDF97) batch_inv_tile<CDF97>(a, sm, local, w, lane);
+    else if (DD && im.wavelet == DD137) batch_inv_tile<DD ? DD137 : CDF53>(a, sm, local, w, lane);
+    else batch_inv_tile<CDF53>(a, sm, local, w, lane);
 }
 
 // Host-to-device copy through kernel arguments (at most kUploadWords words
@@ -592,10 +639,12 @@ struct Grid {
     int ntx, ntiles, blocks;
 };
 
-Grid fused_grid(int W, int H, int HQ)
+template <int WAV>
+Grid fused_grid(int W, int H)
 {
+    constexpr int HQ = Shape<WAV>::HQ;
     const int QW = (W + 1) / 2, QH = (H + 1) / 2;
-    const int ix = TX - 2 * HQ, iy = TY - 2 * HQ;
+    const int ix = TX - 2 * HQ, iy = tile_h<WAV>() - 2 * HQ;
     Grid g;
     g.ntx = (QW + ix - 1) / ix;
     g.ntiles = g.ntx * ((QH + iy - 1) / iy);
@@ -603,57 +652,79 @@ Grid fused_grid(int W, int H, int HQ)
     return g;
 }
 
+template <int WAV>
+hipError_t fused_fwd(bool fp64, const FwdArgs &a, hipStream_t s)
+{
+    const Grid g = fused_grid<WAV>(a.W, a.H);
+    const dim3 grid(g.blocks), block(NTHREADS);
+    return fp64 ? launch(k_fused_forward<WAV, double>, grid, block, s, a, g.ntx, g.ntiles)
+                : launch(k_fused_forward<WAV, float>, grid, block, s, a, g.ntx, g.ntiles);
+}
+
+template <int WAV>
+hipError_t fused_inv(bool fp64, const InvArgs &a, hipStream_t s)
+{
+    const Grid g = fused_grid<WAV>(a.W, a.H);
+    const dim3 grid(g.blocks), block(NTHREADS);
+    return fp64 ? launch(k_fused_inverse<WAV, double>, grid, block, s, a, g.ntx, g.ntiles)
+                : launch(k_fused_inverse<WAV, float>, grid, block, s, a, g.ntx, g.ntiles);
+}
+
 }  // namespace
 
 hipError_t launch_fused_forward(int wavelet, bool fp64, const FwdArgs &a, hipStream_t s)
 {
-    const int HQ = wavelet == CDF97 ? 2 : 1;
-    const Grid g = fused_grid(a.W, a.H, HQ);
-    const dim3 grid(g.blocks), block(NTHREADS);
-    if (wavelet == CDF53)
-        return fp64 ? launch(k_fused_forward<CDF53, double>, grid, block, s, a, g.ntx, g.ntiles)
-                    : launch(k_fused_forward<CDF53, float>, grid, block, s, a, g.ntx, g.ntiles);
-    if (wavelet == CDF97)
-        return fp64 ? launch(k_fused_forward<CDF97, double>, grid, block, s, a, g.ntx, g.ntiles)
-                    : launch(k_fused_forward<CDF97, float>, grid, block, s, a, g.ntx, g.ntiles);
-    return hipErrorInvalidValue;
+    switch (wavelet) {
+    case CDF53: return fused_fwd<CDF53>(fp64, a, s);
+    case CDF97: return fused_fwd<CDF97>(fp64, a, s);
+    case DD137: return fused_fwd<DD137>(fp64, a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_fused_inverse(int wavelet, bool fp64, const InvArgs &a, hipStream_t s)
 {
-    const int HQ = wavelet == CDF97 ? 2 : 1;
-    const Grid g = fused_grid(a.W, a.H, HQ);
-    const dim3 grid(g.blocks), block(NTHREADS);
-    if (wavelet == CDF53)
-        return fp64 ? launch(k_fused_inverse<CDF53, double>, grid, block, s, a, g.ntx, g.ntiles)
-                    : launch(k_fused_inverse<CDF53, float>, grid, block, s, a, g.ntx, g.ntiles);
-    if (wavelet == CDF97)
-        return fp64 ? launch(k_fused_inverse<CDF97, double>, grid, block, s, a, g.ntx, g.ntiles)
-                    : launch(k_fused_inverse<CDF97, float>, grid, block, s, a, g.ntx, g.ntiles);
-    return hipErrorInvalidValue;
+    switch (wavelet) {
+    case CDF53: return fused_inv<CDF53>(fp64, a, s);
+    case CDF97: return fused_inv<CDF97>(fp64, a, s);
+    case DD137: return fused_inv<DD137>(fp64, a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 long long fused_tile_count(int wavelet, int W, int H)
 {
     if (W < 2 || H < 2) return 0;
-    const int HQ = wavelet == CDF97 ? 2 : 1;
+    int HQ, TYw;
+    switch (wavelet) {
+    case CDF53: HQ = Shape<CDF53>::HQ; TYw = tile_h<CDF53>(); break;
+    case CDF97: HQ = Shape<CDF97>::HQ; TYw = tile_h<CDF97>(); break;
+    case DD137: HQ = Shape<DD137>::HQ; TYw = tile_h<DD137>(); break;
+    default: return 0;
+    }
     const long long QW = (W + 1LL) / 2, QH = (H + 1LL) / 2;
-    const int ix = TX - 2 * HQ, iy = TY - 2 * HQ;
+    const int ix = TX - 2 * HQ, iy = TYw - 2 * HQ;
     return ((QW + ix - 1) / ix) * ((QH + iy - 1) / iy);
 }
 
-hipError_t launch_batch_forward(bool fp64, const BatchLevel &b, hipStream_t s)
+hipError_t launch_batch_forward(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s)
 {
     const dim3 grid((b.ntiles + 7) / 8 * 8), block(NTHREADS);
-    return fp64 ? launch(k_batch_forward<double>, grid, block, s, b)
-                : launch(k_batch_forward<float>, grid, block, s, b);
+    if (has_dd)
+        return fp64 ? launch(k_batch_forward<double, true>, grid, block, s, b)
+                    : launch(k_batch_forward<float, true>, grid, block, s, b);
+    return fp64 ? launch(k_batch_forward<double, false>, grid, block, s, b)
+                : launch(k_batch_forward<float, false>, grid, block, s, b);
 }
 
-hipError_t launch_batch_inverse(bool fp64, const BatchLevel &b, hipStream_t s)
+hipError_t launch_batch_inverse(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s)
 {
     const dim3 grid((b.ntiles + 7) / 8 * 8), block(NTHREADS);
-    return fp64 ? launch(k_batch_inverse<double>, grid, block, s, b)
-                : launch(k_batch_inverse<float>, grid, block, s, b);
+    if (has_dd)
+        return fp64 ? launch(k_batch_inverse<double, true>, grid, block, s, b)
+                    : launch(k_batch_inverse<float, true>, grid, block, s, b);
+    return fp64 ? launch(k_batch_inverse<double, false>, grid, block, s, b)
+                : launch(k_batch_inverse<float, false>, grid, block, s, b);
 }
 
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s)

@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libdwt2.so")
 
 OK, E_ARG, E_SIZE, E_UNSUPPORTED, E_WORKSPACE, E_ALIAS, E_HIP, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
-CDF53, CDF97 = 0, 1
+CDF53, CDF97, DD137 = 0, 1, 2
 EXT_WHOLE_SYMMETRIC = 0
 NORM_UNIT_DC, NORM_PAPER = 0, 1
 SCHEME_AUTO, SCHEME_MONOLITHIC_STAR, SCHEME_SWELDENS, SCHEME_IWAHASHI, SCHEME_ROWCOL = 0, 1, 2, 3, 4
@@ -24,7 +24,8 @@ SCHEME_MONOLITHIC_STAR_TILE = 5
 SCHEME_MONOLITHIC, SCHEME_EXPLOSIVE, SCHEME_EXPLOSIVE_STAR = 6, 7, 8
 SCHEME_IWAHASHI_STAR, SCHEME_POLYPHASE_STAR = 9, 10
 
-WAVELETS = {"cdf53": CDF53, "cdf97": CDF97, CDF53: CDF53, CDF97: CDF97}
+WAVELETS = {"cdf53": CDF53, "cdf97": CDF97, "dd137": DD137, CDF53: CDF53, CDF97: CDF97,
+            DD137: DD137}
 NORMS = {"unit_dc": NORM_UNIT_DC, "paper": NORM_PAPER, NORM_UNIT_DC: NORM_UNIT_DC,
          NORM_PAPER: NORM_PAPER}
 SCHEMES = {"auto": SCHEME_AUTO, "monolithic*": SCHEME_MONOLITHIC_STAR,

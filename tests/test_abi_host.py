@@ -112,7 +112,12 @@ def test_size_errors():
 
 
 def test_unsupported():
-    assert _fwd(wavelet=2) == dwt2.E_UNSUPPORTED
+    for bad in (3, -1, 99):  # one past the last wavelet id, and garbage
+        assert _fwd(wavelet=bad) == dwt2.E_UNSUPPORTED
+    # DD 13/7 runs in the fused kernel only
+    for scheme in ("monolithic*-tile", "sweldens", "iwahashi", "rowcol", "monolithic", "explosive",
+                   "explosive*", "iwahashi*", "polyphase*"):
+        assert _fwd(wavelet=2, opt=dwt2.make_options(scheme=scheme)) == dwt2.E_UNSUPPORTED
     assert _fwd(ext=1) == dwt2.E_UNSUPPORTED
     o = dwt2.make_options()
     o.norm = 2

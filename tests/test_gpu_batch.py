@@ -24,7 +24,7 @@ from paper_1605_00561_amd import dwt2  # noqa: E402
 MIXED = [(2, 2, "cdf53", 1, None), (3, 5, "cdf97", 2, None), (37, 22, "cdf97", 3, 41),
          (129, 64, "cdf53", 4, None), (300, 500, "cdf97", 5, 333), (1030, 770, "cdf53", 3, None),
          (520, 131, "cdf97", 1, None), (64, 3000, "cdf53", 6, 80), (1000, 999, "cdf97", 7, None),
-         (258, 130, "cdf53", 2, None)]
+         (258, 130, "cdf53", 2, None), (77, 45, "dd137", 3, None), (513, 260, "dd137", 4, 520)]
 
 
 def mixed_inputs(seed=200):
@@ -51,7 +51,7 @@ def single(x, wav, lev, norm, arith, inverse=False):
 @pytest.mark.parametrize("norm", ["unit_dc", "paper"])
 def test_mixed_batch_equals_single_calls(norm, arith):
     xs, hosts = mixed_inputs()
-    # image 10 shares image 4's source with another wavelet and depth
+    # the last image shares image 4's source with another wavelet and depth
     xs.append(xs[4])
     hosts.append(hosts[4])
     cfg = [(w, l) for (_, _, w, l, _) in MIXED] + [("cdf53", 4)]

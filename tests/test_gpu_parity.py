@@ -216,6 +216,39 @@ def test_fp64_arithmetic_small_and_multilevel(wav):
     run_case(x, wav, 3, "unit_dc", "monolithic*", pitch=211, arithmetic="fp64", bar=FP64_BAR)
 
 
+# --- DD 13/7 (fused kernel only) ------------------------------------------------
+@pytest.mark.parametrize("arith", ["fp32", "fp64"])
+def test_dd137_single_and_multi_level(arith):
+    """The third wavelet of the paper's Table 1: four-tap operators (halo of three
+    quadruples) through the fused Monolithic* kernel."""
+    rng = np.random.default_rng(110)
+    bar = FP64_BAR if arith == "fp64" else None
+    for (w, h) in SMALL_SHAPES:
+        x = rng.integers(0, 256, size=(h, w)).astype(np.float32)
+        for norm in ("unit_dc", "paper"):
+            run_case(x, "dd137", 1, norm, "monolithic*", arithmetic=arith, bar=bar)
+    for (w, h) in [(258, 130), (301, 203), (1000, 999), (64, 3000)]:
+        x = rng.integers(0, 256, size=(h, w)).astype(np.float32)
+        for lev in sorted({2, 3, max_levels(w, h, 7)}):
+            run_case(x, "dd137", lev, "unit_dc", "monolithic*", arithmetic=arith, bar=bar)
+    x = rng.integers(0, 256, size=(97, 203)).astype(np.float32)
+    run_case(x, "dd137", 3, "unit_dc", "monolithic*", pitch=211, arithmetic=arith, bar=bar)
+    for (w, h) in [(64, 64), (33, 17), (2, 2), (3, 3), (6, 5)]:
+        x = rng.integers(0, 256, size=(h, w)).astype(np.float32)
+        run_case(x, "dd137", max_levels(w, h, 30), "unit_dc", "monolithic*", arithmetic=arith,
+                 bar=bar)
+
+
+def test_dd137_constant_image_and_normalisation_relation():
+    c = np.full((90, 131), 77.0, dtype=np.float32)
+    y = to_host(dwt2.forward(to_dev(c), "dd137", 3))
+    check(y, oracle.forward(c.astype(np.float64), "dd137", 3), False, "constant dd137")
+    x = wl.uniform_u8(301, 187, seed=111)
+    u = to_host(dwt2.forward(to_dev(x), "dd137", 4, "unit_dc"))
+    p = to_host(dwt2.forward(to_dev(x), "dd137", 4, "paper"))
+    assert np.array_equal(p, u * paper_ratio(301, 187, 4))
+
+
 # --- full workload sizes ---------------------------------------------------------
 def test_workload_cdf53_512():
     x = wl.workload_image("cdf53_512_l1")

@@ -23,7 +23,7 @@ def random_requests(n, seed, lo=16, hi=1500):
     for _ in range(n):
         w = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
         h = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
-        wav = "cdf53" if rng.random() < 0.5 else "cdf97"
+        wav = ("cdf53", "cdf97", "dd137")[int(rng.integers(0, 3))]
         lev = int(rng.integers(1, max_levels(w, h, 6) + 1))
         inverse = bool(rng.random() < 0.5)
         x = torch.from_numpy(rng.integers(0, 256, size=(h, w)).astype(np.float32)).to(dev())
