@@ -27,6 +27,7 @@ line:
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import statistics
@@ -103,14 +104,30 @@ def main():
     stream = torch.cuda.current_stream()
     npx = W * H
 
+    # The timed step calls the C ABI directly with arguments marshalled once, so
+    # that the host enqueues faster than the GPU drains (the torch conveniences
+    # cost tens of microseconds per call, enough to leave the GPU idle between
+    # the two ~100 us kernels and to inflate the event times).
+    lib = dwt2.library()
+    opt = dwt2.make_options(scheme="monolithic*")
+    st, nws = dwt2.dwt2_workspace_bytes(wav, lev, W, H, opt)
+    assert st == dwt2.OK and nws == 0  # one level needs no workspace
+    hs = stream.cuda_stream
+    wcode = dwt2.WAVELETS[wav]
+    fargs = [(wcode, lev, W, H, xs[k].data_ptr(), xs[k].stride(0), ys[k].data_ptr(), ys[k].stride(0),
+              dwt2.EXT_WHOLE_SYMMETRIC, ctypes.byref(opt), None, 0, hs) for k in range(NSETS)]
+    iargs = [(wcode, lev, W, H, ys[k].data_ptr(), ys[k].stride(0), zs[k].data_ptr(), zs[k].stride(0),
+              dwt2.EXT_WHOLE_SYMMETRIC, ctypes.byref(opt), None, 0, hs) for k in range(NSETS)]
+    status = []
+
     def step(i, ev=None):
         k = i % NSETS
         if ev is not None:
             ev[0].record(stream)
-        dwt2.forward(xs[k], wav, lev, out=ys[k], scheme="monolithic*")
+        status.append(lib.dwt2_forward(*fargs[k]))
         if ev is not None:
             ev[1].record(stream)
-        dwt2.inverse(ys[k], wav, lev, out=zs[k], scheme="monolithic*")
+        status.append(lib.dwt2_inverse(*iargs[k]))
         if ev is not None:
             ev[2].record(stream)
 
@@ -125,6 +142,8 @@ def main():
         step(i, evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if any(st != dwt2.OK for st in status):
+        raise dwt2.Dwt2Error(next(st for st in status if st != dwt2.OK), "timed step")
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     fwd_ms = [e[0].elapsed_time(e[1]) for e in evs]
     inv_ms = [e[1].elapsed_time(e[2]) for e in evs]
@@ -184,11 +203,14 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
     stream = torch.cuda.current_stream()
     table = {}
     for name in ("monolithic*", "monolithic*:fp64", "monolithic*-tile", "monolithic", "sweldens",
-                 "iwahashi", "iwahashi*", "explosive", "explosive*", "polyphase*", "rowcol"):
-        scheme, _, arith = name.partition(":")
+                 "iwahashi", "iwahashi*", "explosive", "explosive*", "polyphase*", "rowcol",
+                 "monolithic*@cdf53", "monolithic*@dd137"):
+        name_w, _, wname = name.partition("@")
+        scheme, _, arith = name_w.partition(":")
         arith = arith or "auto"
+        wav_ = wname or wav
         ws = None
-        st, nbytes = dwt2.dwt2_workspace_bytes(wav, lev, xs[0].shape[1], xs[0].shape[0],
+        st, nbytes = dwt2.dwt2_workspace_bytes(wav_, lev, xs[0].shape[1], xs[0].shape[0],
                                                dwt2.make_options(scheme=scheme))
         if nbytes:
             ws = torch.empty(nbytes, dtype=torch.uint8, device=xs[0].device)
@@ -197,14 +219,14 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
             f = dwt2.forward if direction == "forward" else dwt2.inverse
             src, dst = (xs, ys) if direction == "forward" else (ys, zs)
             for i in range(2):
-                f(src[i % NSETS], wav, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws,
+                f(src[i % NSETS], wav_, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws,
                   arithmetic=arith)
             ms = []
             for i in range(reps):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                f(src[i % NSETS], wav, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws,
+                f(src[i % NSETS], wav_, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws,
                   arithmetic=arith)
                 e1.record(stream)
                 ms.append((e0, e1))
@@ -231,10 +253,38 @@ def _median_us(torch, fn, reps):
     return statistics.median(a.elapsed_time(b) for a, b in ev) * 1e3
 
 
+def _graph_us(torch, fn, n=20, reps=5):
+    """Device time per call of fn, from a HIP graph of n back-to-back calls
+    (host launch overhead excluded; what remains is the kernels and the gaps
+    between graph nodes).  Median over reps replays."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(n):
+            fn()
+    stream = torch.cuda.current_stream()
+    g.replay()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3 / n)
+    return statistics.median(ts)
+
+
 def pyramid_table(dwt2, torch, workloads, reps):
     """Per-level forward and inverse of the fused kernel on the 16384^2 CDF 9/7
     five-level workload: each level's input size timed as a one-level call on
-    the LL band the previous level produced, plus the whole five-level call."""
+    the LL band the previous level produced (device time per call from a HIP
+    graph of back-to-back calls), plus the whole five-level call."""
     name = "cdf97_16384_l5"
     spec = workloads.WORKLOADS[name]
     W, H, wav, lev = spec["width"], spec["height"], spec["wavelet"], spec["levels"]
@@ -249,8 +299,8 @@ def pyramid_table(dwt2, torch, workloads, reps):
         src = cur.contiguous()
         dst = torch.empty_like(src)
         back = torch.empty_like(src)
-        tf = _median_us(torch, lambda i: dwt2.forward(src, wav, 1, out=dst), reps)
-        ti = _median_us(torch, lambda i: dwt2.inverse(dst, wav, 1, out=back), reps)
+        tf = _graph_us(torch, lambda: dwt2.forward(src, wav, 1, out=dst))
+        ti = _graph_us(torch, lambda: dwt2.inverse(dst, wav, 1, out=back))
         npx = w * h
         levels.append({"level": k + 1, "width": w, "height": h,
                        "forward_us": round(tf, 2), "inverse_us": round(ti, 2),
