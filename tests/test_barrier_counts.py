@@ -1,0 +1,84 @@
+"""The barrier counts of the built kernels equal the paper's Table 1 (CPU only).
+
+Each kernel source is compiled to gfx950 assembly with the library's own
+flags, and the `s_barrier` instructions of every kernel are counted.  A tile
+kernel runs one lifting scheme on one tile, so its static count is the number
+of memory barriers Table 1 lists for that scheme and wavelet (transcribed in
+tests/golden/).  The fused Monolithic* kernels inline the tile body twice (the
+vector path for interior tiles and the scalar path for edge tiles), so their
+count is twice Table 1's.  The row-column kernels share nothing across
+threads and have none.
+"""
+import concurrent.futures as cf
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_1605_00561_amd import build
+from scheme_model import read_table1
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TABLE1 = read_table1(os.path.join(ROOT, "tests", "golden", "table1_barriers_operations.txt"))
+WAVELET_IDS = {0: "cdf53", 1: "cdf97", 2: "dd137"}
+SCHEME_IDS = {2: "sweldens", 3: "iwahashi", 5: "monolithic*", 6: "monolithic", 7: "explosive",
+              8: "explosive*", 9: "iwahashi*", 10: "polyphase*"}
+
+
+def _barriers(source, tmpdir):
+    out = os.path.join(tmpdir, source + ".s")
+    cmd = [build.HIPCC, *build.CFLAGS, "--cuda-device-only", "-S",
+           os.path.join(build.CSRC, source), "-o", out]
+    subprocess.run(cmd, check=True, capture_output=True)
+    text = open(out).read()
+    parts = re.split(r"^\s*\.type\s+(\S+),@function\s*$", text, flags=re.M)
+    counts = {}
+    for name, body in zip(parts[1::2], parts[2::2]):
+        body = body.split("; Kernel info:")[0]
+        dem = subprocess.run(["c++filt", name], capture_output=True, text=True).stdout.strip()
+        counts[dem] = len(re.findall(r"^\s*s_barrier\b", body, re.M))
+    return counts
+
+
+@pytest.fixture(scope="module")
+def counts(tmp_path_factory):
+    if shutil.which(build.HIPCC) is None and not os.path.exists(build.HIPCC):
+        pytest.skip("hipcc not available")
+    tmp = str(tmp_path_factory.mktemp("isa"))
+    with cf.ThreadPoolExecutor(3) as ex:
+        parts = list(ex.map(lambda s: _barriers(s, tmp),
+                            ["tile_kernels.hip", "fused_kernels.hip", "rowcol_kernels.hip"]))
+    merged = {}
+    for p in parts:
+        merged.update(p)
+    return merged
+
+
+def _find(counts, pattern):
+    hits = [v for k, v in counts.items() if re.search(pattern, k)]
+    assert len(hits) == 1, (pattern, [k for k in counts if re.search(pattern, k)])
+    return hits[0]
+
+
+@pytest.mark.parametrize("direction", ["forward", "inverse"])
+def test_tile_kernels_have_table1_barriers(counts, direction):
+    for wid in (0, 1):
+        for sid, scheme in SCHEME_IDS.items():
+            n = _find(counts, rf"k_tile_{direction}<{wid}, {sid}>")
+            assert n == TABLE1[(WAVELET_IDS[wid], scheme)][0], (direction, WAVELET_IDS[wid], scheme)
+
+
+@pytest.mark.parametrize("direction", ["forward", "inverse"])
+def test_fused_kernels_have_two_barriers_per_pair(counts, direction):
+    for wid, wav in WAVELET_IDS.items():
+        for t in ("float", "double"):
+            n = _find(counts, rf"k_fused_{direction}<{wid}, {t}>")
+            assert n == 2 * TABLE1[(wav, "monolithic*")][0], (direction, wav, t)
+
+
+def test_rowcol_kernels_have_no_barriers(counts):
+    for k, v in counts.items():
+        if "k_rows_" in k or "k_cols_" in k:
+            assert v == 0, k
