@@ -63,15 +63,17 @@ def parse():
                     help="skip the 512-image batched workload")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving-loop request stream")
+    ap.add_argument("--no-tiles", action="store_true",
+                    help="skip the tile-height table (every built height per wavelet and size)")
     ap.add_argument("--no-copy", action="store_true",
                     help="skip the device-to-device copy (the bandwidth and counter reference)")
     return ap.parse_args()
 
 
-def traffic_from_profiles(tag: str):
+def traffic_from_profiles(tag: str, kernel: str):
     """HBM bytes per launch of the dominant kernel from the committed PMC summary
     (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when it is
-    absent or was taken on different kernel sources."""
+    absent, was taken on different kernel sources or of another kernel."""
     path = os.path.join(ROOT, "profiles", f"{tag}_hbm_counters.json")
     if not os.path.exists(path):
         return None
@@ -79,7 +81,7 @@ def traffic_from_profiles(tag: str):
         import hashlib
         rec = json.load(open(path))
         blob = b"".join(open(os.path.join(ROOT, s), "rb").read() for s in rec["sources"])
-        if hashlib.sha256(blob).hexdigest() != rec["sources_sha256"]:
+        if hashlib.sha256(blob).hexdigest() != rec["sources_sha256"] or rec["kernel"] != kernel:
             return None
         return int(round(rec["bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
@@ -206,11 +208,12 @@ def main():
 
     fwd_mean = statistics.fmean(fwd_ms)
     achieved = BYTES_PER_PX * npx / (fwd_mean * 1e-3) / 1e9
-    traffic = traffic_from_profiles("fused_forward_cdf97_8192")
+    kernel = f"k_fused_forward<{wcode}, {dwt2.tile_rows(wav, W, H)}, float>"
+    traffic = traffic_from_profiles("fused_forward_cdf97_8192", kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "k_fused_forward<CDF97>",
+                "kernel": kernel,
                 "algorithmic_bytes_per_launch": int(BYTES_PER_PX * npx),
                 "mean_launch_us": round(fwd_mean * 1e3, 2),
                 "inverse_mean_launch_us": round(statistics.fmean(inv_ms) * 1e3, 2)}
@@ -226,6 +229,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "cdf97_8192x8192_l1_fwd+inv", "wavelet": wav, "width": W,
                    "height": H, "levels": lev, "scheme": "monolithic*",
+                   "tile_rows": {"forward": dwt2.tile_rows(wav, W, H),
+                                 "inverse": dwt2.tile_rows(wav, W, H, inverse=True)},
                    "image": "cosine gradient (period 512) + N(0, 8^2), clipped to [0, 255]",
                    "buffer_sets": NSETS},
         "device_warmup_steps": n_dev_warm,
@@ -235,6 +240,8 @@ def main():
 
     if not args.no_schemes:
         out["schemes"] = scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, args.scheme_reps)
+    if not args.no_tiles:
+        out["tiles"] = tile_table(dwt2, torch, xs[0], ys[0], zs[0], args.scheme_reps)
     if not args.no_pyramid:
         del xs, ys, zs
         torch.cuda.empty_cache()
@@ -255,8 +262,34 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def tile_table(dwt2, torch, x, y, z, reps, sizes=(8192, 2048, 512)):
+    """Forward / inverse device time (us, HIP-graph timed) of one fused level
+    at every built tile height, on n x n crops of the workload image, with the
+    height the selection rule picks; then dwt2_autotune's pick for the full
+    8192^2 9/7 level (the table is emptied again afterwards)."""
+    out = {}
+    for wav in ("cdf97", "cdf53", "dd137"):
+        for n in sizes:
+            xc = x[:n, :n].contiguous()
+            yc, zc = torch.empty_like(xc), torch.empty_like(xc)
+            row = {"rule": [dwt2.tile_rows(wav, n, n), dwt2.tile_rows(wav, n, n, inverse=True)]}
+            for r in dwt2.TILE_ROWS[wav]:
+                tf = _graph_us(torch, lambda: dwt2.forward(xc, wav, 1, out=yc, tile_rows=r), reps=reps)
+                ti = _graph_us(torch, lambda: dwt2.inverse(yc, wav, 1, out=zc, tile_rows=r), reps=reps)
+                row[f"rows{r}_us"] = [round(tf, 2), round(ti, 2)]
+            out[f"{wav}@{n}"] = row
+    dwt2.dwt2_tune_reset()
+    n = x.shape[0]
+    dwt2.autotune(x, "cdf97", 1, repeats=20, out=y)
+    dwt2.autotune(y, "cdf97", 1, inverse=True, repeats=20, out=z)
+    out[f"autotuned_cdf97@{n}"] = [dwt2.tile_rows("cdf97", n, n),
+                                   dwt2.tile_rows("cdf97", n, n, inverse=True)]
+    dwt2.dwt2_tune_reset()
+    return out
+
+
 def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
-    stream = torch.cuda.current_stream()
+    """Device time of one level per scheme (HIP-graph timed, as _graph_us)."""
     table = {}
     for name in ("monolithic*", "monolithic*:fp64", "monolithic*-tile", "monolithic", "sweldens",
                  "iwahashi", "iwahashi*", "explosive", "explosive*", "polyphase*", "rowcol",
@@ -273,23 +306,11 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
         res = {}
         for direction in ("forward", "inverse"):
             f = dwt2.forward if direction == "forward" else dwt2.inverse
-            src, dst = (xs, ys) if direction == "forward" else (ys, zs)
-            for i in range(2):
-                f(src[i % NSETS], wav_, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws,
-                  arithmetic=arith)
-            ms = []
-            for i in range(reps):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                f(src[i % NSETS], wav_, lev, scheme=scheme, out=dst[i % NSETS], workspace=ws,
-                  arithmetic=arith)
-                e1.record(stream)
-                ms.append((e0, e1))
-            torch.cuda.synchronize()
-            t = statistics.median(a.elapsed_time(b) for a, b in ms)
-            gbs = BYTES_PER_PX * npx / (t * 1e-3) / 1e9
-            res[direction] = {"us": round(t * 1e3, 2), "Gpixel_s": round(npx / (t * 1e-3) / 1e9, 1),
+            src, dst = (xs[0], ys[0]) if direction == "forward" else (ys[0], zs[0])
+            us = _graph_us(torch, lambda: f(src, wav_, lev, scheme=scheme, out=dst, workspace=ws,
+                                            arithmetic=arith), reps=reps)
+            gbs = BYTES_PER_PX * npx / (us * 1e-6) / 1e9
+            res[direction] = {"us": round(us, 2), "Gpixel_s": round(npx / (us * 1e-6) / 1e9, 1),
                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
         table[name] = res
     return table

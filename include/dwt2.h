@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define DWT2_VERSION 2
+#define DWT2_VERSION 3
 
 /* Status codes. */
 #define DWT2_OK 0
@@ -130,12 +130,29 @@ typedef enum dwt2_scheme {
  */
 typedef enum dwt2_arith { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_ARITH_FP64 = 2 } dwt2_arith;
 
-/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO). */
+/*
+ * Tile height of the fused MONOLITHIC_STAR kernel.  A work-group lifts one
+ * overlapping tile of 64 x (4 * tile_rows) quadruples (128 x 8 * tile_rows
+ * pixels) in registers, the block-based layout of Sec. 6; tall tiles re-read
+ * fewer halo rows, short tiles give small levels more work-groups.  Built
+ * heights (FP32 lifting): 5/3 {2, 3}, 9/7 {2, 3, 4}, DD 13/7 {3, 6};
+ * FP64 lifting: 5/3 {3}, 9/7 {4}, DD 13/7 {6}.  Every height gives bitwise
+ * identical coefficients (each tile takes its centring constant from a fixed
+ * band of rows that contains its outputs), so the choice changes speed only.
+ * 0 selects per level: the entry dwt2_autotune recorded for this wavelet,
+ * direction and level size, else the tallest height that still gives at
+ * least 1024 tiles (four per compute unit), else the shortest.  Another
+ * value, or a nonzero value with another scheme or with the batched calls,
+ * returns DWT2_E_UNSUPPORTED.
+ */
+
+/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO, 0). */
 typedef struct dwt2_options {
     int norm;        /* dwt2_norm */
     int scheme;      /* dwt2_scheme */
     int arithmetic;  /* dwt2_arith */
-    int reserved[5]; /* must be zero */
+    int tile_rows;   /* fused-kernel tile height (above); 0 = automatic */
+    int reserved[4]; /* must be zero */
 } dwt2_options;
 
 /*
@@ -299,6 +316,63 @@ int dwt2_server_replay(dwt2_server *server, const dwt2_request *requests,
 
 /* Finish every queued request, stop the threads and free the handle. */
 int dwt2_server_destroy(dwt2_server *server);
+
+/*
+ * Tile-height autotuning
+ * ----------------------
+ * Not in the paper, which fixes one work-group size per platform (Sec. 6).
+ * The tile height only trades halo re-reads against work-groups in flight
+ * (see dwt2_options), so it is tuned by measurement, per level size.
+ *
+ * dwt2_autotune runs the transform that dwt2_forward (inverse == 0) or
+ * dwt2_inverse (inverse != 0) runs with the same arguments and leaves the same
+ * result in dst.  Along the way it runs each level `repeats` times at every
+ * built FP32 height (two passes), times the runs with HIP events on `stream`,
+ * and records the fastest height for (wavelet, direction, level width, level
+ * height) in a table shared by the process (entries are replaced; the table
+ * holds at most 4096 entries, further sizes are not recorded).  Later calls
+ * with tile_rows == 0 use the recorded height of a level of that exact size.
+ * Argument rules are those of dwt2_forward; the scheme must be AUTO or
+ * MONOLITHIC_STAR, the arithmetic AUTO or FP32 and tile_rows 0, else
+ * DWT2_E_UNSUPPORTED; repeats must be in [1, 1000], else DWT2_E_ARG.  The
+ * call blocks until its work on `stream` is done and must not be captured in
+ * a graph.  The table is locked internally: any thread may call any function.
+ */
+int dwt2_autotune(int inverse, dwt2_wavelet wavelet, int levels, int width, int height,
+                  const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
+                  dwt2_ext ext, const dwt2_options *opt, void *workspace, size_t workspace_bytes,
+                  int repeats, hipStream_t stream);
+
+/*
+ * Height the fused kernel uses for one width x height level of a call with
+ * these options (tile_rows, the FP64 height, the table, or the rule above).
+ * Writes *rows.  DWT2_E_UNSUPPORTED when the options do not select the fused
+ * kernel; DWT2_E_ARG / DWT2_E_SIZE for bad sizes or a null pointer.
+ */
+int dwt2_tile_rows(int inverse, dwt2_wavelet wavelet, int width, int height,
+                   const dwt2_options *opt, int *rows);
+
+/*
+ * The table as text, one entry per line: "wavelet inverse width height rows"
+ * (decimal, single spaces, '\n' after each line), in ascending key order.
+ * Writes up to cap bytes of it plus a terminating NUL into buf (buf may be
+ * NULL when cap is 0) and the full length without the NUL into *len.
+ * DWT2_E_SIZE when cap <= *len (buf then holds no partial line: buf[0] is NUL
+ * if cap > 0).
+ */
+int dwt2_tune_export(char *buf, size_t cap, size_t *len);
+
+/*
+ * Add the entries of text in dwt2_tune_export's format to the table
+ * (replacing entries of the same key).  The whole text is checked first: a
+ * malformed line, an unknown wavelet, a size below 2 or a height that is not
+ * built for that wavelet leaves the table unchanged and returns DWT2_E_ARG;
+ * more entries than the table holds, DWT2_E_SIZE.
+ */
+int dwt2_tune_import(const char *text);
+
+/* Empty the table. */
+int dwt2_tune_reset(void);
 
 /* Static text for a status code ("unknown status" for others). */
 const char *dwt2_status_string(int status);

@@ -9,6 +9,11 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <array>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -28,7 +33,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Config {
-    int wavelet, norm, scheme, arithmetic;
+    int wavelet, norm, scheme, arithmetic, tile_rows;
 };
 
 int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c)
@@ -40,12 +45,14 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     c->norm = DWT2_NORM_UNIT_DC;
     c->scheme = DWT2_SCHEME_AUTO;
     c->arithmetic = DWT2_ARITH_AUTO;
+    c->tile_rows = 0;
     if (opt) {
         for (int r : opt->reserved)
             if (r != 0) return DWT2_E_ARG;
         c->norm = opt->norm;
         c->scheme = opt->scheme;
         c->arithmetic = opt->arithmetic;
+        c->tile_rows = opt->tile_rows;
     }
     if (c->arithmetic < DWT2_ARITH_AUTO || c->arithmetic > DWT2_ARITH_FP64) return DWT2_E_UNSUPPORTED;
     if (c->norm != DWT2_NORM_UNIT_DC && c->norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
@@ -58,7 +65,46 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     if (c->arithmetic == DWT2_ARITH_AUTO) c->arithmetic = DWT2_ARITH_FP32;
     // DD 13/7's four-tap operators are implemented by the fused kernel only.
     if (c->wavelet == DWT2_DD137 && c->scheme != DWT2_SCHEME_MONOLITHIC_STAR) return DWT2_E_UNSUPPORTED;
+    if (c->tile_rows != 0 &&
+        (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR ||
+         !dwt2::fused_rows_supported(c->wavelet, c->arithmetic == DWT2_ARITH_FP64, c->tile_rows)))
+        return DWT2_E_UNSUPPORTED;
     return DWT2_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile height of the fused kernel per level.  Tuned entries, keyed by
+// (wavelet, inverse, level width, level height), live in one table per
+// process; g_tune_size lets calls skip the lock while it is empty.
+using TuneKey = std::array<int, 4>;
+constexpr size_t kTuneMax = 4096;
+// Four work-groups per compute unit (256 CUs): below this a level is short
+// of work-groups and shorter tiles win; above it taller tiles (fewer halo
+// rows re-read) win, as measured over 512^2 .. 8192^2 levels.
+constexpr long long kFillTiles = 1024;
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+std::atomic<size_t> g_tune_size{0};
+
+int rule_rows(int wavelet, int W, int H)
+{
+    int pick = dwt2::kFusedRows[wavelet][0];  // heights are listed in ascending order
+    for (int r : dwt2::kFusedRows[wavelet])
+        if (r > 0 && dwt2::fused_tile_count(wavelet, r, W, H) >= kFillTiles) pick = r;
+    return pick;
+}
+
+int choose_rows(const Config &c, bool inverse, int W, int H)
+{
+    if (c.arithmetic == DWT2_ARITH_FP64) return dwt2::kFusedRowsFp64[c.wavelet];
+    if (c.tile_rows) return c.tile_rows;
+    if (g_tune_size.load(std::memory_order_acquire)) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(TuneKey{c.wavelet, inverse ? 1 : 0, W, H});
+        if (it != g_tune.end()) return it->second;
+    }
+    return rule_rows(c.wavelet, W, H);
 }
 
 // Level k (0-based) transforms a ws[k] x hs[k] block; each must be >= 2 x 2.
@@ -146,6 +192,7 @@ size_t span_bytes(ptrdiff_t pitch, int w, int h)
 
 struct Checked {
     Config cfg;
+    int levels;
     int ws[kMaxLevels], hs[kMaxLevels];
     Layout lay;
 };
@@ -158,6 +205,7 @@ int check_call(dwt2_wavelet wavelet, int levels, int width, int height, const fl
     if (st != DWT2_OK) return st;
     st = geometry(levels, width, height, c->ws, c->hs);
     if (st != DWT2_OK) return st;
+    c->levels = levels;
     if (!src || !dst) return DWT2_E_ARG;
     if (src_pitch < width || dst_pitch < width) return DWT2_E_ARG;
     if (((uintptr_t)src & 3) || ((uintptr_t)dst & 3)) return DWT2_E_ARG;
@@ -170,6 +218,54 @@ int check_call(dwt2_wavelet wavelet, int levels, int width, int height, const fl
         (overlap(workspace, c->lay.total, src, ns) || overlap(workspace, c->lay.total, dst, nd)))
         return DWT2_E_ALIAS;
     return DWT2_OK;
+}
+
+// Arguments of forward level k (0-based).  Level k reads the image (k = 0)
+// or LL_k; LL_j (1-based j) lives in workspace buffer A for odd j, B for even
+// j, with pitch = its width; the last level writes LL into dst.
+dwt2::FwdArgs forward_level(const Checked &c, int k, const float *src, ptrdiff_t src_pitch,
+                            float *dst, ptrdiff_t dst_pitch, void *workspace)
+{
+    char *wsb = (char *)workspace;
+    float *buf[2] = {(float *)(wsb + c.lay.a_off), (float *)(wsb + c.lay.b_off)};
+    const int levels = c.levels, W = c.ws[k], H = c.hs[k];
+    dwt2::FwdArgs a;
+    a.in = k == 0 ? src : buf[(k - 1) & 1];
+    a.in_pitch = k == 0 ? src_pitch : (ptrdiff_t)W;
+    a.det = dst;
+    a.det_pitch = dst_pitch;
+    a.W = W;
+    a.H = H;
+    a.s = level_scale(c.cfg.wavelet, c.cfg.norm);
+    a.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
+    a.quantum = c.cfg.norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
+    a.ll = k == levels - 1 ? dst : buf[k & 1];
+    a.ll_pitch = k == levels - 1 ? dst_pitch : (ptrdiff_t)((W + 1) / 2);
+    return a;
+}
+
+// Arguments of inverse level k: it rebuilds its W_k x H_k input from LL_{k+1}
+// (src at the last level, else its workspace buffer) and the details in src,
+// into dst (k = 0) or LL_k's buffer.
+dwt2::InvArgs inverse_level(const Checked &c, int k, const float *src, ptrdiff_t src_pitch,
+                            float *dst, ptrdiff_t dst_pitch, void *workspace)
+{
+    char *wsb = (char *)workspace;
+    float *buf[2] = {(float *)(wsb + c.lay.a_off), (float *)(wsb + c.lay.b_off)};
+    const int levels = c.levels, W = c.ws[k], H = c.hs[k];
+    dwt2::InvArgs a;
+    a.ll = k == levels - 1 ? src : buf[k & 1];
+    a.ll_pitch = k == levels - 1 ? src_pitch : (ptrdiff_t)((W + 1) / 2);
+    a.det = src;
+    a.det_pitch = src_pitch;
+    a.W = W;
+    a.H = H;
+    a.inv_s = inverse_scale(c.cfg.wavelet, c.cfg.norm);
+    a.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
+    a.quantum = c.cfg.norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
+    a.out = k == 0 ? dst : buf[(k - 1) & 1];
+    a.out_pitch = k == 0 ? dst_pitch : (ptrdiff_t)W;
+    return a;
 }
 
 int hip_status(hipError_t e)
@@ -224,40 +320,18 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
                         workspace, workspace_bytes, &c);
     if (st != DWT2_OK) return st;
     char *wsb = (char *)workspace;
-    float *buf[2] = {(float *)(wsb + c.lay.a_off), (float *)(wsb + c.lay.b_off)};
     float *tmp = (float *)(wsb + c.lay.t_off);
-    const dwt2::Scale s = level_scale(c.cfg.wavelet, c.cfg.norm);
-    const float *in = src;
-    ptrdiff_t in_pitch = src_pitch;
     for (int k = 0; k < levels; k++) {
-        const int W = c.ws[k], H = c.hs[k];
-        dwt2::FwdArgs a;
-        a.in = in;
-        a.in_pitch = in_pitch;
-        a.det = dst;
-        a.det_pitch = dst_pitch;
-        a.W = W;
-        a.H = H;
-        a.s = s;
-        a.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
-        a.quantum = c.cfg.norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
-        if (k == levels - 1) {
-            a.ll = dst;
-            a.ll_pitch = dst_pitch;
-        } else {  // level k+1 (1-based) writes its LL to buffer A if odd, B if even
-            a.ll = buf[k & 1];
-            a.ll_pitch = (W + 1) / 2;
-        }
+        const dwt2::FwdArgs a = forward_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
         hipError_t e;
         if (c.cfg.scheme == DWT2_SCHEME_ROWCOL)
-            e = dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, W, stream);
+            e = dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
-            e = dwt2::launch_fused_forward(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64, a, stream);
+            e = dwt2::launch_fused_forward(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
+                                           choose_rows(c.cfg, false, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
         if (e != hipSuccess) return hip_status(e);
-        in = a.ll;
-        in_pitch = a.ll_pitch;
     }
     return DWT2_OK;
 }
@@ -272,43 +346,18 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
                         workspace, workspace_bytes, &c);
     if (st != DWT2_OK) return st;
     char *wsb = (char *)workspace;
-    float *buf[2] = {(float *)(wsb + c.lay.a_off), (float *)(wsb + c.lay.b_off)};
     float *tmp = (float *)(wsb + c.lay.t_off);
-    const dwt2::Scale r = inverse_scale(c.cfg.wavelet, c.cfg.norm);
-    // Level k (0-based) reconstructs its W_k x H_k input from LL_{k+1} and
-    // the details in src.  LL_j (1-based j) lives in buffer A for odd j, B
-    // for even j, exactly as in the forward direction.
-    const float *ll = src;
-    ptrdiff_t ll_pitch = src_pitch;
     for (int k = levels - 1; k >= 0; k--) {
-        const int W = c.ws[k], H = c.hs[k];
-        dwt2::InvArgs a;
-        a.ll = ll;
-        a.ll_pitch = ll_pitch;
-        a.det = src;
-        a.det_pitch = src_pitch;
-        a.W = W;
-        a.H = H;
-        a.inv_s = r;
-        a.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
-        a.quantum = c.cfg.norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
-        if (k == 0) {
-            a.out = dst;
-            a.out_pitch = dst_pitch;
-        } else {  // output is LL_k (1-based k): buffer A if k odd, B if even
-            a.out = buf[(k - 1) & 1];
-            a.out_pitch = W;
-        }
+        const dwt2::InvArgs a = inverse_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
         hipError_t e;
         if (c.cfg.scheme == DWT2_SCHEME_ROWCOL)
-            e = dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, W, stream);
+            e = dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
-            e = dwt2::launch_fused_inverse(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64, a, stream);
+            e = dwt2::launch_fused_inverse(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
+                                           choose_rows(c.cfg, true, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_inverse(c.cfg.wavelet, c.cfg.scheme, a, stream);
         if (e != hipSuccess) return hip_status(e);
-        ll = a.out;
-        ll_pitch = a.out_pitch;
     }
     return DWT2_OK;
 }
@@ -361,7 +410,7 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
     if (count < 0 || count > DWT2_BATCH_MAX || (count > 0 && !images)) return DWT2_E_ARG;
     int st = parse(DWT2_CDF53, ext, opt, &p->cfg);
     if (st != DWT2_OK) return st;
-    if (p->cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR) return DWT2_E_UNSUPPORTED;
+    if (p->cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || p->cfg.tile_rows != 0) return DWT2_E_UNSUPPORTED;
     p->rec.resize(count);
     p->buf_off[0].resize(count);
     p->buf_off[1].resize(count);
@@ -407,7 +456,7 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
             if (r.levels > k) {
                 const int w = (int)(((long long)r.W + (1LL << k) - 1) >> k);
                 const int h = (int)(((long long)r.H + (1LL << k) - 1) >> k);
-                acc += dwt2::fused_tile_count(r.wavelet, w, h);
+                acc += dwt2::fused_tile_count(r.wavelet, dwt2::kBatchRows[r.wavelet], w, h);
             }
             if (acc > INT_MAX - 8) return DWT2_E_ARG;
         }
@@ -503,4 +552,192 @@ DWT2_EXPORT int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext
                                    hipStream_t stream)
 {
     return run_batch(true, images, count, ext, opt, workspace, workspace_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Tile-height autotuning.
+
+namespace {
+
+// Mean time of `repeats` back-to-back launches of one level at `rows`, in ms.
+int time_level(bool inverse, const Checked &c, const void *args, int rows, int repeats,
+               hipEvent_t e0, hipEvent_t e1, hipStream_t stream, float *ms)
+{
+    auto run = [&]() {
+        return inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows,
+                                                    *(const dwt2::InvArgs *)args, stream)
+                       : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows,
+                                                    *(const dwt2::FwdArgs *)args, stream);
+    };
+    hipError_t e = hipEventRecord(e0, stream);
+    for (int i = 0; i < repeats && e == hipSuccess; i++) e = run();
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e != hipSuccess) return hip_status(e);
+    *ms /= (float)repeats;
+    return DWT2_OK;
+}
+
+int tune(bool inverse, const Checked &c, const float *src, ptrdiff_t src_pitch, float *dst,
+         ptrdiff_t dst_pitch, void *workspace, int repeats, hipStream_t stream, hipEvent_t e0,
+         hipEvent_t e1)
+{
+    const int *cand = dwt2::kFusedRows[c.cfg.wavelet];
+    for (int j = 0; j < c.levels; j++) {
+        const int k = inverse ? c.levels - 1 - j : j;
+        dwt2::FwdArgs fa;
+        dwt2::InvArgs ia;
+        const void *args;
+        if (inverse) {
+            ia = inverse_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
+            args = &ia;
+        } else {
+            fa = forward_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
+            args = &fa;
+        }
+        // Two passes over the heights; each keeps its faster pass.  Every run
+        // writes the same level output, so the next level reads the result.
+        float best[dwt2::kFusedRowsMax];
+        for (int pass = 0; pass < 2; pass++)
+            for (int i = 0; i < dwt2::kFusedRowsMax && cand[i] > 0; i++) {
+                float ms = 0.0f;
+                const int st = time_level(inverse, c, args, cand[i], repeats, e0, e1, stream, &ms);
+                if (st != DWT2_OK) return st;
+                best[i] = pass == 0 ? ms : std::min(best[i], ms);
+            }
+        int pick = 0;
+        for (int i = 1; i < dwt2::kFusedRowsMax && cand[i] > 0; i++)
+            if (best[i] < best[pick]) pick = i;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const TuneKey key{c.cfg.wavelet, inverse ? 1 : 0, c.ws[k], c.hs[k]};
+        if (g_tune.size() < kTuneMax || g_tune.count(key)) g_tune[key] = cand[pick];
+        g_tune_size.store(g_tune.size(), std::memory_order_release);
+    }
+    return DWT2_OK;
+}
+
+// One line of the exported table: "wavelet inverse width height rows".
+bool parse_line(const char *p, const char *end, TuneKey *key, int *rows)
+{
+    long long v[5];
+    for (int i = 0; i < 5; i++) {
+        if (i > 0) {
+            if (p >= end || *p != ' ') return false;
+            p++;
+        }
+        if (p >= end || *p < '0' || *p > '9') return false;
+        long long x = 0;
+        while (p < end && *p >= '0' && *p <= '9') {
+            x = x * 10 + (*p - '0');
+            if (x > INT_MAX) return false;
+            p++;
+        }
+        v[i] = x;
+    }
+    if (p != end) return false;
+    const int wavelet = (int)v[0], inverse = (int)v[1], w = (int)v[2], h = (int)v[3];
+    if (wavelet > DWT2_DD137 || inverse > 1 || w < 2 || h < 2) return false;
+    if (!dwt2::fused_rows_supported(wavelet, false, (int)v[4])) return false;
+    *key = TuneKey{wavelet, inverse, w, h};
+    *rows = (int)v[4];
+    return true;
+}
+
+}  // namespace
+
+DWT2_EXPORT int dwt2_autotune(int inverse, dwt2_wavelet wavelet, int levels, int width, int height,
+                              const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
+                              dwt2_ext ext, const dwt2_options *opt, void *workspace,
+                              size_t workspace_bytes, int repeats, hipStream_t stream)
+{
+    Checked c;
+    int st = check_call(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext, opt,
+                        workspace, workspace_bytes, &c);
+    if (st != DWT2_OK) return st;
+    if (c.cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || c.cfg.arithmetic != DWT2_ARITH_FP32 ||
+        c.cfg.tile_rows != 0)
+        return DWT2_E_UNSUPPORTED;
+    if (repeats < 1 || repeats > 1000) return DWT2_E_ARG;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess)
+        st = tune(inverse != 0, c, src, src_pitch, dst, dst_pitch, workspace, repeats, stream, e0, e1);
+    else
+        st = hip_status(e);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    return st;
+}
+
+DWT2_EXPORT int dwt2_tile_rows(int inverse, dwt2_wavelet wavelet, int width, int height,
+                               const dwt2_options *opt, int *rows)
+{
+    if (!rows) return DWT2_E_ARG;
+    Config cfg;
+    int st = parse(wavelet, DWT2_EXT_WHOLE_SYMMETRIC, opt, &cfg);
+    if (st != DWT2_OK) return st;
+    if (cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR) return DWT2_E_UNSUPPORTED;
+    if (width < 1 || height < 1) return DWT2_E_ARG;
+    if (width < 2 || height < 2 || (long long)width * height > kMaxPixels) return DWT2_E_SIZE;
+    *rows = choose_rows(cfg, inverse != 0, width, height);
+    return DWT2_OK;
+}
+
+DWT2_EXPORT int dwt2_tune_export(char *buf, size_t cap, size_t *len)
+{
+    if (!len || (cap > 0 && !buf)) return DWT2_E_ARG;
+    std::string text;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : g_tune) {
+            const TuneKey &k = kv.first;
+            text += std::to_string(k[0]) + ' ' + std::to_string(k[1]) + ' ' + std::to_string(k[2]) +
+                    ' ' + std::to_string(k[3]) + ' ' + std::to_string(kv.second) + '\n';
+        }
+    }
+    *len = text.size();
+    if (cap <= text.size()) {
+        if (cap > 0) buf[0] = '\0';
+        return DWT2_E_SIZE;
+    }
+    std::copy(text.begin(), text.end(), buf);
+    buf[text.size()] = '\0';
+    return DWT2_OK;
+}
+
+DWT2_EXPORT int dwt2_tune_import(const char *text)
+{
+    if (!text) return DWT2_E_ARG;
+    std::vector<std::pair<TuneKey, int>> add;
+    for (const char *p = text; *p;) {
+        const char *nl = p;
+        while (*nl && *nl != '\n') nl++;
+        TuneKey key;
+        int rows;
+        if (!parse_line(p, nl, &key, &rows)) return DWT2_E_ARG;
+        add.emplace_back(key, rows);
+        p = *nl ? nl + 1 : nl;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    size_t fresh = 0;
+    std::vector<TuneKey> seen;
+    for (const auto &kv : add)
+        if (!g_tune.count(kv.first) && std::find(seen.begin(), seen.end(), kv.first) == seen.end()) {
+            seen.push_back(kv.first);
+            fresh++;
+        }
+    if (g_tune.size() + fresh > kTuneMax) return DWT2_E_SIZE;
+    for (const auto &kv : add) g_tune[kv.first] = kv.second;
+    g_tune_size.store(g_tune.size(), std::memory_order_release);
+    return DWT2_OK;
+}
+
+DWT2_EXPORT int dwt2_tune_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_size.store(0, std::memory_order_release);
+    return DWT2_OK;
 }

@@ -125,9 +125,21 @@ hipError_t launch_tile_forward(int wavelet, int scheme, const FwdArgs &a, hipStr
 hipError_t launch_tile_inverse(int wavelet, int scheme, const InvArgs &a, hipStream_t s);
 
 // Fused Monolithic* (registers + DPP, LDS only at wavefront seams).
+// A tile is 64 quadruple columns by 4 * rows quadruple rows; `rows` (rows per
+// wavefront) is one of kFusedRows[wavelet] for FP32 lifting and
+// kFusedRowsFp64[wavelet] for FP64 (hipErrorInvalidValue otherwise).  Every
+// height gives bitwise identical coefficients: the centring constant of a
+// tile is taken from a fixed cell of rows that contains the tile's outputs.
 // fp64: lift in double-precision registers (samples stay FP32 in memory).
-hipError_t launch_fused_forward(int wavelet, bool fp64, const FwdArgs &a, hipStream_t s);
-hipError_t launch_fused_inverse(int wavelet, bool fp64, const InvArgs &a, hipStream_t s);
+constexpr int kFusedRowsMax = 3;
+constexpr int kFusedRows[3][kFusedRowsMax] = {{2, 3, 0}, {2, 3, 4}, {3, 6, 0}};
+constexpr int kFusedRowsFp64[3] = {3, 4, 6};
+bool fused_rows_supported(int wavelet, bool fp64, int rows);
+hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, const FwdArgs &a, hipStream_t s);
+hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, const InvArgs &a, hipStream_t s);
+// Tiles of the fused kernel for one W x H level at `rows` (0 when a side is
+// below 2 or the height is not built).
+long long fused_tile_count(int wavelet, int rows, int W, int H);
 
 // Batched fused launches.  One record per image, in device memory; a level
 // launch covers the tiles of every image that has that level.  The buffer
@@ -162,8 +174,8 @@ struct BatchLevel {
 // image records and the tile-start table, each 256-byte aligned.
 size_t batch_table_bytes(int count, int lmax);
 
-// Tiles of the fused kernel for one W x H level (0 when a side is below 2).
-long long fused_tile_count(int wavelet, int W, int H);
+// Tile height of the batched launches, per wavelet.
+constexpr int kBatchRows[3] = {3, 4, 6};
 // has_dd: the batch holds a DD 13/7 image (its taller tile needs more LDS).
 hipError_t launch_batch_forward(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s);
 hipError_t launch_batch_inverse(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s);

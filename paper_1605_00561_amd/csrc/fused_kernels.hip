@@ -7,8 +7,9 @@
 // (barrier), the scalar predict parts, T_{-P1} (barrier).
 //
 // Mapping.  A work-group owns one overlapping tile of 64 x (NW * RB)
-// quadruples (K quadruples of halo per side, K = lifting pairs), as in the
-// paper's block-based method (Sec. 6).  Lane c of wavefront w holds the
+// quadruples (HQ quadruples of halo per side), as in the paper's block-based
+// method (Sec. 6); RB, the rows per wavefront, is a template parameter with
+// a few built values per wavelet (the host picks one per level).  Lane c of wavefront w holds the
 // quadruples of column c in the tile rows w, w + NW, w + 2 NW, ... in
 // registers: the rows are interleaved across the wavefronts, so at any time
 // the work-group's loads and stores cover NW adjacent rows, which measured
@@ -22,11 +23,16 @@
 //     LDS plane, and the barrier the scheme places before the step makes them
 //     visible.  Two plane buffers alternate between predict and update, so
 //     Monolithic* keeps its two barriers per lifting pair.
-// LDS is 26 KB (FP32), so occupancy is set by registers.
+// LDS is at most 29 KB (FP32), so occupancy is set by registers.
 //
 // Borders: whole-sample symmetric extension, samples read from mirrored
-// positions.  Centring: each tile subtracts the rounded mean c of its middle
-// quadruple row and adds c * ll_gain back to LL (exact by linearity).
+// positions.  Centring: each tile subtracts a rounded local mean c from its
+// samples and adds c * ll_gain back to LL (exact by linearity).  c is the mean
+// of the tile's columns in the middle row of its centring cell, a band of
+// CELL quadruple rows that holds the tile's outputs; CELL is a multiple of the
+// output height of every built tile height, so every output sees the same c
+// and the same arithmetic whatever the tile height, and the coefficients are
+// bitwise independent of it.
 // Tiles are numbered so that each XCD (work-group id mod 8) takes a
 // contiguous row-major run, so neighbouring tiles share their halo in L2.
 #include <string.h>
@@ -40,31 +46,45 @@ constexpr int TX = 64;  // quadruple columns per tile (one per lane)
 constexpr int NW = 4;   // wavefronts per work-group (tile row j * NW + w)
 constexpr int NTHREADS = TX * NW;
 
-// Tile shape per wavelet: RB quadruple rows per wavefront, HQ quadruples of
-// halo per side (how far one level's lifting pairs reach: 1 per pair for the
-// two-tap CDF operators, 3 for DD 13/7's four-tap pair), PAD padding rows of
-// the LDS planes (the operators' vertical reach).
+// Per wavelet: HQ quadruples of halo per side (how far one level's lifting
+// pairs reach: 1 per pair for the two-tap CDF operators, 3 for DD 13/7's
+// four-tap pair), PAD padding rows of the LDS planes (the operators' vertical
+// reach), CELL quadruple rows of a centring cell.
 template <int WAV>
-struct Shape;
+struct Halo;
 template <>
-struct Shape<CDF53> {
-    static constexpr int RB = 4, HQ = 1, PAD = 1;
+struct Halo<CDF53> {
+    static constexpr int HQ = 1, PAD = 1, CELL = 30;
 };
 template <>
-struct Shape<CDF97> {
-    static constexpr int RB = 4, HQ = 2, PAD = 1;
+struct Halo<CDF97> {
+    static constexpr int HQ = 2, PAD = 1, CELL = 24;
 };
 template <>
-struct Shape<DD137> {
-    static constexpr int RB = 6, HQ = 3, PAD = 2;
+struct Halo<DD137> {
+    static constexpr int HQ = 3, PAD = 2, CELL = 18;
 };
-template <int WAV>
-constexpr int tile_h() { return NW * Shape<WAV>::RB; }
-template <int WAV>
-constexpr int plane_rows() { return tile_h<WAV>() + 2 * Shape<WAV>::PAD; }
-// Elements of the two plane buffers (two components each) a tile needs.
-template <int WAV>
-constexpr int plane_elems() { return 2 * 2 * plane_rows<WAV>() * TX; }
+
+// Tile geometry at RB quadruple rows per wavefront: TY rows of which the
+// middle IY are output rows (IX of the TX columns), and the LDS plane size.
+template <int WAV, int RB>
+struct Geo {
+    static constexpr int HQ = Halo<WAV>::HQ, PAD = Halo<WAV>::PAD, CELL = Halo<WAV>::CELL;
+    static constexpr int TY = NW * RB, IX = TX - 2 * HQ, IY = TY - 2 * HQ;
+    static constexpr int PLANE_ROWS = TY + 2 * PAD;
+    // Elements of the two plane buffers (two components each).
+    static constexpr int PLANE_ELEMS = 2 * 2 * PLANE_ROWS * TX;
+    static_assert(IY > 0 && CELL % IY == 0, "a tile's output rows must lie in one centring cell");
+    // Quadruple row whose mean centres tile row tr (before mirroring).
+    __device__ static int centre_row(int tr) { return tr * IY / CELL * CELL + CELL / 2; }
+};
+
+template <int WAV, int I = 0>
+constexpr bool built_rows(int rb)
+{
+    if constexpr (I == kFusedRowsMax) return false;
+    else return kFusedRows[WAV][I] == rb || built_rows<WAV, I + 1>(rb);
+}
 
 enum { LL = 0, HL = 1, LH = 2, HH = 3 };
 
@@ -117,12 +137,13 @@ __device__ __forceinline__ int xcd_tile(int ntiles)
 
 // Row planes in LDS: [buffer][component][tile row + PAD][lane]; the PAD rows
 // above and below the tile are read only by halo rows.
-template <int WAV, typename T>
+template <int WAV, int RB, typename T>
 struct Planes {
     T *base;
     __device__ __forceinline__ T &at(int b, int comp, int r, int c) const
     {
-        return base[((b * 2 + comp) * plane_rows<WAV>() + r + Shape<WAV>::PAD) * TX + c];
+        using G = Geo<WAV, RB>;
+        return base[((b * 2 + comp) * G::PLANE_ROWS + r + G::PAD) * TX + c];
     }
 };
 
@@ -181,9 +202,9 @@ struct Across {
     template <int D>
     __device__ __forceinline__ T get() const { return lane_shift<D>(v); }
 };
-template <int WAV, typename T>
+template <int WAV, int RB, typename T>
 struct Down {
-    const Planes<WAV, T> &pl;
+    const Planes<WAV, RB, T> &pl;
     int b, comp, r, lane;
     template <int D>
     __device__ __forceinline__ T get() const { return pl.at(b, comp, r + D, lane); }
@@ -196,13 +217,13 @@ struct Down {
 // vertical sum.  All reads are of pre-step values.  The inverse reads the
 // post-step values and subtracts, except the P1 P1* term, which keeps its sign.
 template <int WAV, bool INV, int RB, typename T>
-__device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane, int k)
+__device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane, int k)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
         const int r = tile_row(j, w);
-        const T vll = taps<WAV, true>((T)0, k, Down<WAV, T>{pl, 0, 0, r, lane});
-        const T vhl = taps<WAV, true>((T)0, k, Down<WAV, T>{pl, 0, 1, r, lane});
+        const T vll = taps<WAV, true>((T)0, k, Down<WAV, RB, T>{pl, 0, 0, r, lane});
+        const T vhl = taps<WAV, true>((T)0, k, Down<WAV, RB, T>{pl, 0, 1, r, lane});
         const T hll = taps<WAV, true>((T)0, k, Across<T>{q[j][LL]});
         const T hlh = taps<WAV, true>((T)0, k, Across<T>{q[j][LH]});
         const T dll = taps<WAV, true>((T)0, k, Across<T>{vll});
@@ -222,13 +243,13 @@ __device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, T>
 //   LL += U1 HL + U1* LH + U1 U1* HH;  HL += U1* HH;  LH += U1 HH
 // with the rows of plane buffer 1.
 template <int WAV, bool INV, int RB, typename T>
-__device__ __forceinline__ void update_step(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane, int k)
+__device__ __forceinline__ void update_step(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane, int k)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
         const int r = tile_row(j, w);
-        const T vlh = taps<WAV, false>((T)0, k, Down<WAV, T>{pl, 1, 0, r, lane});
-        const T vhh = taps<WAV, false>((T)0, k, Down<WAV, T>{pl, 1, 1, r, lane});
+        const T vlh = taps<WAV, false>((T)0, k, Down<WAV, RB, T>{pl, 1, 0, r, lane});
+        const T vhh = taps<WAV, false>((T)0, k, Down<WAV, RB, T>{pl, 1, 1, r, lane});
         const T hhl = taps<WAV, false>((T)0, k, Across<T>{q[j][HL]});
         const T hhh = taps<WAV, false>((T)0, k, Across<T>{q[j][HH]});
         const T dhh = taps<WAV, false>((T)0, k, Across<T>{vhh});
@@ -247,7 +268,7 @@ __device__ __forceinline__ void update_step(T (&q)[RB][4], const Planes<WAV, T> 
 // The components a step reads across rows: LL, HL for the predict (buffer
 // 0), LH, HH for the update (buffer 1).
 template <int WAV, int RB, typename T>
-__device__ __forceinline__ void publish_predict(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane)
+__device__ __forceinline__ void publish_predict(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
@@ -256,7 +277,7 @@ __device__ __forceinline__ void publish_predict(T (&q)[RB][4], const Planes<WAV,
     }
 }
 template <int WAV, int RB, typename T>
-__device__ __forceinline__ void publish_update(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane)
+__device__ __forceinline__ void publish_update(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
@@ -311,7 +332,7 @@ __device__ __forceinline__ void scalar_unpredict(T (&q)[RB][4], T p)
 }
 
 template <int WAV, int RB, typename T>
-__device__ __forceinline__ void forward_tile(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane)
+__device__ __forceinline__ void forward_tile(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane)
 {
     using C = Coef<WAV, T>;
 #pragma unroll
@@ -328,7 +349,7 @@ __device__ __forceinline__ void forward_tile(T (&q)[RB][4], const Planes<WAV, T>
 }
 
 template <int WAV, int RB, typename T>
-__device__ __forceinline__ void inverse_tile(T (&q)[RB][4], const Planes<WAV, T> &pl, int w, int lane)
+__device__ __forceinline__ void inverse_tile(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane)
 {
     using C = Coef<WAV, T>;
 #pragma unroll
@@ -352,12 +373,12 @@ __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)
 
 // Horizontal fast path: the tile's 128 pixel columns lie inside the image and
 // rows are 8-byte aligned, so each pixel-row pair is one float2 per lane.
-template <int WAV, typename T, bool VEC>
+template <int WAV, int RB, typename T, bool VEC>
 __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int tr, int w, int lane)
 {
-    constexpr int HQ = Shape<WAV>::HQ, RB = Shape<WAV>::RB, TY = tile_h<WAV>();
-    constexpr int IX = TX - 2 * HQ, IY = TY - 2 * HQ;
-    const Planes<WAV, T> pl{lds};
+    using G = Geo<WAV, RB>;
+    constexpr int HQ = G::HQ, TY = G::TY, IX = G::IX, IY = G::IY;
+    const Planes<WAV, RB, T> pl{lds};
     const int W = a.W, H = a.H;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1, WH = W >> 1, HHr = H >> 1;
     const int qc = tc * IX - HQ + lane;
@@ -382,7 +403,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int t
     float c;
     {
         float a0, a1, a2, a3;
-        load(tr * IY - HQ + TY / 2, a0, a1, a2, a3);
+        load(G::centre_row(tr), a0, a1, a2, a3);
         const float sum = wave_sum((a0 + a1) + (a2 + a3));
         c = rintf(sum * (1.0f / (4 * TX)) / a.quantum) * a.quantum;
     }
@@ -411,21 +432,35 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int t
     }
 }
 
-template <int WAV, typename T, bool VEC>
+template <int WAV, int RB, typename T, bool VEC>
 __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int tr, int w, int lane)
 {
-    constexpr int HQ = Shape<WAV>::HQ, RB = Shape<WAV>::RB, TY = tile_h<WAV>();
-    constexpr int IX = TX - 2 * HQ, IY = TY - 2 * HQ;
-    const Planes<WAV, T> pl{lds};
+    using G = Geo<WAV, RB>;
+    constexpr int HQ = G::HQ, TY = G::TY, IX = G::IX, IY = G::IY;
+    const Planes<WAV, RB, T> pl{lds};
     const int W = a.W, H = a.H;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1;
     const int qc = tc * IX - HQ + lane;
     const int cl = ws_mirror(2 * qc, W) >> 1, ch = ws_mirror(2 * qc + 1, W) >> 1;
     const int qr0 = tr * IY - HQ;  // quadruple row of tile row 0
 
+    // All loads are issued before the centring reduction, which needs its own
+    // load to complete first.
+    float raw[RB][4];
+#pragma unroll
+    for (int j = 0; j < RB; j++) {
+        const int qr = qr0 + tile_row(j, w);
+        const int rl = ws_mirror(2 * qr, H) >> 1, rh = ws_mirror(2 * qr + 1, H) >> 1;
+        const float *lrow = a.det + (ptrdiff_t)rl * a.det_pitch;
+        const float *hrow = a.det + (ptrdiff_t)(QH + rh) * a.det_pitch;
+        raw[j][LL] = a.ll[(ptrdiff_t)rl * a.ll_pitch + cl];
+        raw[j][HL] = lrow[QW + ch];
+        raw[j][LH] = hrow[cl];
+        raw[j][HH] = hrow[QW + ch];
+    }
     float c;
     {
-        const int rm = ws_mirror(2 * (tr * IY - HQ + TY / 2), H) >> 1;
+        const int rm = ws_mirror(2 * G::centre_row(tr), H) >> 1;
         const float sum = wave_sum(a.ll[(ptrdiff_t)rm * a.ll_pitch + cl]);
         c = rintf(sum * (1.0f / TX) / (a.ll_gain * a.quantum)) * a.quantum;
     }
@@ -434,14 +469,10 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int t
     T q[RB][4];
 #pragma unroll
     for (int j = 0; j < RB; j++) {
-        const int qr = qr0 + tile_row(j, w);
-        const int rl = ws_mirror(2 * qr, H) >> 1, rh = ws_mirror(2 * qr + 1, H) >> 1;
-        const float *lrow = a.det + (ptrdiff_t)rl * a.det_pitch;
-        const float *hrow = a.det + (ptrdiff_t)(QH + rh) * a.det_pitch;
-        q[j][LL] = ((T)a.ll[(ptrdiff_t)rl * a.ll_pitch + cl] - (T)cll) * (T)a.inv_s.ll;
-        q[j][HL] = lrow[QW + ch];
-        q[j][LH] = hrow[cl];
-        q[j][HH] = (T)hrow[QW + ch] * (T)a.inv_s.hh;
+        q[j][LL] = ((T)raw[j][LL] - (T)cll) * (T)a.inv_s.ll;
+        q[j][HL] = raw[j][HL];
+        q[j][LH] = raw[j][LH];
+        q[j][HH] = (T)raw[j][HH] * (T)a.inv_s.hh;
     }
 
     inverse_tile(q, pl, w, lane);
@@ -470,11 +501,11 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int t
     }
 }
 
-template <int WAV, typename T>
+template <int WAV, int RB, typename T>
 __global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, int ntiles)
 {
-    constexpr int HQ = Shape<WAV>::HQ;
-    __shared__ T sm[plane_elems<WAV>()];
+    constexpr int HQ = Halo<WAV>::HQ;
+    __shared__ T sm[Geo<WAV, RB>::PLANE_ELEMS];
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;  // uniform over the work-group
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
@@ -483,16 +514,16 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, 
     const bool vec = px_first >= 0 && px_first + 2 * TX <= a.W &&
                      (((uintptr_t)a.in | (uintptr_t)(a.in_pitch * 4)) & 7) == 0;
     if (vec)
-        fwd_body<WAV, T, true>(a, sm, tc, tr, w, lane);
+        fwd_body<WAV, RB, T, true>(a, sm, tc, tr, w, lane);
     else
-        fwd_body<WAV, T, false>(a, sm, tc, tr, w, lane);
+        fwd_body<WAV, RB, T, false>(a, sm, tc, tr, w, lane);
 }
 
-template <int WAV, typename T>
+template <int WAV, int RB, typename T>
 __global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, int ntiles)
 {
-    constexpr int HQ = Shape<WAV>::HQ;
-    __shared__ T sm[plane_elems<WAV>()];
+    constexpr int HQ = Halo<WAV>::HQ;
+    __shared__ T sm[Geo<WAV, RB>::PLANE_ELEMS];
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
@@ -501,9 +532,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, 
     const bool vec = px_first >= 0 && px_first + 2 * TX <= a.W &&
                      (((uintptr_t)a.out | (uintptr_t)(a.out_pitch * 4)) & 7) == 0;
     if (vec)
-        inv_body<WAV, T, true>(a, sm, tc, tr, w, lane);
+        inv_body<WAV, RB, T, true>(a, sm, tc, tr, w, lane);
     else
-        inv_body<WAV, T, false>(a, sm, tc, tr, w, lane);
+        inv_body<WAV, RB, T, false>(a, sm, tc, tr, w, lane);
 }
 
 // Batched levels.  A work-group finds its image by a search over the tile
@@ -535,35 +566,40 @@ __device__ __forceinline__ int level_size(int n, int k)
 template <int WAV, typename T>
 __device__ __forceinline__ void batch_fwd_tile(const FwdArgs &a, T *lds, int local, int w, int lane)
 {
-    constexpr int HQ = Shape<WAV>::HQ;
+    constexpr int HQ = Halo<WAV>::HQ, RB = kBatchRows[WAV];
     const int ntx = ((a.W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
     const int tc = local % ntx, tr = local / ntx;
     const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
     const bool aligned = (((uintptr_t)a.in | (uintptr_t)(a.in_pitch * 4)) & 7) == 0;
     if (aligned && px_first >= 0 && px_first + 2 * TX <= a.W)
-        fwd_body<WAV, T, true>(a, lds, tc, tr, w, lane);
+        fwd_body<WAV, RB, T, true>(a, lds, tc, tr, w, lane);
     else
-        fwd_body<WAV, T, false>(a, lds, tc, tr, w, lane);
+        fwd_body<WAV, RB, T, false>(a, lds, tc, tr, w, lane);
 }
 template <int WAV, typename T>
 __device__ __forceinline__ void batch_inv_tile(const InvArgs &a, T *lds, int local, int w, int lane)
 {
-    constexpr int HQ = Shape<WAV>::HQ;
+    constexpr int HQ = Halo<WAV>::HQ, RB = kBatchRows[WAV];
     const int ntx = ((a.W + 1) / 2 + TX - 2 * HQ - 1) / (TX - 2 * HQ);
     const int tc = local % ntx, tr = local / ntx;
     const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
     const bool aligned = (((uintptr_t)a.out | (uintptr_t)(a.out_pitch * 4)) & 7) == 0;
     if (aligned && px_first >= 0 && px_first + 2 * TX <= a.W)
-        inv_body<WAV, T, true>(a, lds, tc, tr, w, lane);
+        inv_body<WAV, RB, T, true>(a, lds, tc, tr, w, lane);
     else
-        inv_body<WAV, T, false>(a, lds, tc, tr, w, lane);
+        inv_body<WAV, RB, T, false>(a, lds, tc, tr, w, lane);
 }
 
 // LDS of a batched launch: the largest plane set of the wavelets it may meet
 // (DD 13/7's taller tile only when the batch holds such an image).
-static_assert(plane_elems<CDF53>() == plane_elems<CDF97>(), "CDF tiles share one plane size");
+template <int WAV>
+constexpr int batch_planes() { return Geo<WAV, kBatchRows[WAV]>::PLANE_ELEMS; }
 template <bool DD>
-constexpr int batch_plane_elems() { return DD ? plane_elems<DD137>() : plane_elems<CDF97>(); }
+constexpr int batch_plane_elems()
+{
+    constexpr int cdf = batch_planes<CDF53>() > batch_planes<CDF97>() ? batch_planes<CDF53>() : batch_planes<CDF97>();
+    return DD && batch_planes<DD137>() > cdf ? batch_planes<DD137>() : cdf;
+}
 
 template <typename T, bool DD>
 __global__ __launch_bounds__(NTHREADS) void k_batch_forward(BatchLevel b)
@@ -639,72 +675,119 @@ struct Grid {
     int ntx, ntiles, blocks;
 };
 
-template <int WAV>
+long long tile_count(int HQ, int TY, long long W, long long H)
+{
+    if (W < 2 || H < 2) return 0;
+    const long long QW = (W + 1) / 2, QH = (H + 1) / 2;
+    const int ix = TX - 2 * HQ, iy = TY - 2 * HQ;
+    return ((QW + ix - 1) / ix) * ((QH + iy - 1) / iy);
+}
+
+template <int WAV, int RB>
 Grid fused_grid(int W, int H)
 {
-    constexpr int HQ = Shape<WAV>::HQ;
-    const int QW = (W + 1) / 2, QH = (H + 1) / 2;
-    const int ix = TX - 2 * HQ, iy = tile_h<WAV>() - 2 * HQ;
+    using G = Geo<WAV, RB>;
     Grid g;
-    g.ntx = (QW + ix - 1) / ix;
-    g.ntiles = g.ntx * ((QH + iy - 1) / iy);
+    g.ntx = ((W + 1) / 2 + G::IX - 1) / G::IX;
+    g.ntiles = (int)tile_count(G::HQ, G::TY, W, H);
     g.blocks = (g.ntiles + 7) / 8 * 8;
     return g;
 }
 
-template <int WAV>
+// FP64 kernels are built at one height per wavelet.
+template <int WAV, int RB>
 hipError_t fused_fwd(bool fp64, const FwdArgs &a, hipStream_t s)
 {
-    const Grid g = fused_grid<WAV>(a.W, a.H);
+    const Grid g = fused_grid<WAV, RB>(a.W, a.H);
     const dim3 grid(g.blocks), block(NTHREADS);
-    return fp64 ? launch(k_fused_forward<WAV, double>, grid, block, s, a, g.ntx, g.ntiles)
-                : launch(k_fused_forward<WAV, float>, grid, block, s, a, g.ntx, g.ntiles);
+    if constexpr (RB == kFusedRowsFp64[WAV])
+        if (fp64) return launch(k_fused_forward<WAV, RB, double>, grid, block, s, a, g.ntx, g.ntiles);
+    if (fp64) return hipErrorInvalidValue;
+    return launch(k_fused_forward<WAV, RB, float>, grid, block, s, a, g.ntx, g.ntiles);
 }
 
-template <int WAV>
+template <int WAV, int RB>
 hipError_t fused_inv(bool fp64, const InvArgs &a, hipStream_t s)
 {
-    const Grid g = fused_grid<WAV>(a.W, a.H);
+    const Grid g = fused_grid<WAV, RB>(a.W, a.H);
     const dim3 grid(g.blocks), block(NTHREADS);
-    return fp64 ? launch(k_fused_inverse<WAV, double>, grid, block, s, a, g.ntx, g.ntiles)
-                : launch(k_fused_inverse<WAV, float>, grid, block, s, a, g.ntx, g.ntiles);
+    if constexpr (RB == kFusedRowsFp64[WAV])
+        if (fp64) return launch(k_fused_inverse<WAV, RB, double>, grid, block, s, a, g.ntx, g.ntiles);
+    if (fp64) return hipErrorInvalidValue;
+    return launch(k_fused_inverse<WAV, RB, float>, grid, block, s, a, g.ntx, g.ntiles);
+}
+
+// The launcher of (wavelet, rows), over the built heights.
+template <bool INV, int WAV, int I = 0>
+hipError_t dispatch_rows(int rows, bool fp64, const void *args, hipStream_t s)
+{
+    if constexpr (I == kFusedRowsMax) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int RB = kFusedRows[WAV][I];
+        if constexpr (RB > 0) {
+            if (rows == RB)
+                return INV ? fused_inv<WAV, RB>(fp64, *(const InvArgs *)args, s)
+                           : fused_fwd<WAV, RB>(fp64, *(const FwdArgs *)args, s);
+        }
+        return dispatch_rows<INV, WAV, I + 1>(rows, fp64, args, s);
+    }
+}
+
+template <bool INV>
+hipError_t dispatch(int wavelet, bool fp64, int rows, const void *args, hipStream_t s)
+{
+    if (!fused_rows_supported(wavelet, fp64, rows)) return hipErrorInvalidValue;
+    switch (wavelet) {
+    case CDF53: return dispatch_rows<INV, CDF53>(rows, fp64, args, s);
+    case CDF97: return dispatch_rows<INV, CDF97>(rows, fp64, args, s);
+    case DD137: return dispatch_rows<INV, DD137>(rows, fp64, args, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static_assert(built_rows<CDF53>(kFusedRowsFp64[CDF53]) && built_rows<CDF97>(kFusedRowsFp64[CDF97]) &&
+                  built_rows<DD137>(kFusedRowsFp64[DD137]),
+              "the FP64 height is one of the built heights");
+static_assert(built_rows<CDF53>(kBatchRows[CDF53]) && built_rows<CDF97>(kBatchRows[CDF97]) &&
+                  built_rows<DD137>(kBatchRows[DD137]),
+              "the batched height is one of the built heights");
+
+int halo_of(int wavelet)
+{
+    switch (wavelet) {
+    case CDF53: return Halo<CDF53>::HQ;
+    case CDF97: return Halo<CDF97>::HQ;
+    case DD137: return Halo<DD137>::HQ;
+    default: return -1;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_fused_forward(int wavelet, bool fp64, const FwdArgs &a, hipStream_t s)
+bool fused_rows_supported(int wavelet, bool fp64, int rows)
 {
-    switch (wavelet) {
-    case CDF53: return fused_fwd<CDF53>(fp64, a, s);
-    case CDF97: return fused_fwd<CDF97>(fp64, a, s);
-    case DD137: return fused_fwd<DD137>(fp64, a, s);
-    default: return hipErrorInvalidValue;
-    }
+    if (wavelet < CDF53 || wavelet > DD137 || rows <= 0) return false;
+    if (fp64) return rows == kFusedRowsFp64[wavelet];
+    for (int r : kFusedRows[wavelet])
+        if (r == rows) return true;
+    return false;
 }
 
-hipError_t launch_fused_inverse(int wavelet, bool fp64, const InvArgs &a, hipStream_t s)
+hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, const FwdArgs &a, hipStream_t s)
 {
-    switch (wavelet) {
-    case CDF53: return fused_inv<CDF53>(fp64, a, s);
-    case CDF97: return fused_inv<CDF97>(fp64, a, s);
-    case DD137: return fused_inv<DD137>(fp64, a, s);
-    default: return hipErrorInvalidValue;
-    }
+    return dispatch<false>(wavelet, fp64, rows, &a, s);
 }
 
-long long fused_tile_count(int wavelet, int W, int H)
+hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, const InvArgs &a, hipStream_t s)
 {
-    if (W < 2 || H < 2) return 0;
-    int HQ, TYw;
-    switch (wavelet) {
-    case CDF53: HQ = Shape<CDF53>::HQ; TYw = tile_h<CDF53>(); break;
-    case CDF97: HQ = Shape<CDF97>::HQ; TYw = tile_h<CDF97>(); break;
-    case DD137: HQ = Shape<DD137>::HQ; TYw = tile_h<DD137>(); break;
-    default: return 0;
-    }
-    const long long QW = (W + 1LL) / 2, QH = (H + 1LL) / 2;
-    const int ix = TX - 2 * HQ, iy = TYw - 2 * HQ;
-    return ((QW + ix - 1) / ix) * ((QH + iy - 1) / iy);
+    return dispatch<true>(wavelet, fp64, rows, &a, s);
+}
+
+long long fused_tile_count(int wavelet, int rows, int W, int H)
+{
+    if (!fused_rows_supported(wavelet, false, rows)) return 0;
+    return tile_count(halo_of(wavelet), NW * rows, W, H);
 }
 
 hipError_t launch_batch_forward(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s)

@@ -38,8 +38,12 @@ SCHEMES.update({v: v for v in list(SCHEMES.values())})
 EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_string",
            "dwt2_last_hip_error", "dwt2_version", "dwt2_batch_workspace_bytes",
            "dwt2_forward_batch", "dwt2_inverse_batch", "dwt2_server_create", "dwt2_server_submit",
-           "dwt2_server_wait", "dwt2_server_replay", "dwt2_server_destroy"]
+           "dwt2_server_wait", "dwt2_server_replay", "dwt2_server_destroy", "dwt2_autotune",
+           "dwt2_tile_rows", "dwt2_tune_export", "dwt2_tune_import", "dwt2_tune_reset"]
 BATCH_MAX = 65536
+# Tile heights the fused kernel is built for (FP32 lifting; FP64: one each).
+TILE_ROWS = {"cdf53": (2, 3), "cdf97": (2, 3, 4), "dd137": (3, 6)}
+TILE_ROWS_FP64 = {"cdf53": 3, "cdf97": 4, "dd137": 6}
 
 
 ARITH_AUTO, ARITH_FP32, ARITH_FP64 = 0, 1, 2
@@ -49,7 +53,7 @@ ARITHS = {"auto": ARITH_AUTO, "fp32": ARITH_FP32, "fp64": ARITH_FP64,
 
 class Options(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_int), ("scheme", ctypes.c_int), ("arithmetic", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("tile_rows", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class Image(ctypes.Structure):
@@ -128,6 +132,14 @@ def _load() -> ctypes.CDLL:
     L.dwt2_last_hip_error.restype = i
     L.dwt2_version.argtypes = []
     L.dwt2_version.restype = i
+    L.dwt2_autotune.argtypes = [i, i, i, i, i, vp, pd, vp, pd, i, ctypes.POINTER(Options), vp, sz,
+                                i, vp]
+    L.dwt2_tile_rows.argtypes = [i, i, i, i, ctypes.POINTER(Options), ctypes.POINTER(i)]
+    L.dwt2_tune_export.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+    L.dwt2_tune_import.argtypes = [ctypes.c_char_p]
+    L.dwt2_tune_reset.argtypes = []
+    for f in ("autotune", "tile_rows", "tune_export", "tune_import", "tune_reset"):
+        getattr(L, "dwt2_" + f).restype = i
     return L
 
 
@@ -138,11 +150,12 @@ def library() -> ctypes.CDLL:
     return _lib
 
 
-def make_options(norm="unit_dc", scheme="auto", arithmetic="auto") -> Options:
+def make_options(norm="unit_dc", scheme="auto", arithmetic="auto", tile_rows=0) -> Options:
     o = Options()
     o.norm = NORMS[norm]
     o.scheme = SCHEMES[scheme]
     o.arithmetic = ARITHS[arithmetic]
+    o.tile_rows = int(tile_rows)
     return o
 
 
@@ -179,6 +192,43 @@ def dwt2_inverse(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch,
     return _lib.dwt2_inverse(WAVELETS[wavelet], levels, width, height, src, src_pitch, dst,
                              dst_pitch, ext, ctypes.byref(opt) if opt is not None else None,
                              workspace, workspace_bytes, stream)
+
+
+def dwt2_autotune(inverse, wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext,
+                  opt: Options | None, workspace, workspace_bytes, repeats, stream) -> int:
+    return _lib.dwt2_autotune(int(bool(inverse)), WAVELETS[wavelet], levels, width, height, src,
+                              src_pitch, dst, dst_pitch, ext,
+                              ctypes.byref(opt) if opt is not None else None, workspace,
+                              workspace_bytes, repeats, stream)
+
+
+def dwt2_tile_rows(inverse, wavelet, width, height, opt: Options | None = None):
+    """(status, rows)."""
+    r = ctypes.c_int(0)
+    st = _lib.dwt2_tile_rows(int(bool(inverse)), WAVELETS[wavelet], width, height,
+                             ctypes.byref(opt) if opt is not None else None, ctypes.byref(r))
+    return st, r.value
+
+
+def dwt2_tune_export():
+    """(status, text)."""
+    n = ctypes.c_size_t(0)
+    st = _lib.dwt2_tune_export(None, 0, ctypes.byref(n))
+    if st not in (OK, E_SIZE):
+        return st, ""
+    while True:  # the table may grow between the two calls
+        buf = ctypes.create_string_buffer(n.value + 1)
+        st = _lib.dwt2_tune_export(buf, len(buf), ctypes.byref(n))
+        if st != E_SIZE:
+            return st, buf.value.decode() if st == OK else ""
+
+
+def dwt2_tune_import(text: str) -> int:
+    return _lib.dwt2_tune_import(text.encode())
+
+
+def dwt2_tune_reset() -> int:
+    return _lib.dwt2_tune_reset()
 
 
 def make_images(entries) -> ctypes.Array:
@@ -274,42 +324,102 @@ def _stream_handle(stream):
     return s.cuda_stream
 
 
-def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
-            workspace=None, stream=None, arithmetic="auto"):
-    """Forward DWT of a (H, W) float32 device tensor; returns the Mallat layout."""
+def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, arithmetic,
+               tile_rows):
+    """Allocate out / workspace as needed and run call(opt, ws, ws_bytes) -> status,
+    a closure over the C entry point with the tensors' pointers."""
     import torch
-    _check_image(img)
-    h, w = img.shape
+    _check_image(x)
+    h, w = x.shape
     if out is None:
-        out = torch.empty((h, w), dtype=torch.float32, device=img.device)
+        out = torch.empty((h, w), dtype=torch.float32, device=x.device)
     _check_image(out)
-    opt = make_options(norm, scheme, arithmetic)
-    ws, nws = _workspace(wavelet, levels, w, h, opt, img.device, workspace)
-    st = dwt2_forward(wavelet, levels, w, h, img.data_ptr(), img.stride(0), out.data_ptr(),
-                      out.stride(0), EXT_WHOLE_SYMMETRIC, opt,
-                      ws.data_ptr() if ws is not None else None, nws, _stream_handle(stream))
+    opt = make_options(norm, scheme, arithmetic, tile_rows)
+    ws, nws = _workspace(wavelet, levels, w, h, opt, x.device, workspace)
+    st = call(out, opt, ws.data_ptr() if ws is not None else None, nws)
     if st != OK:
-        raise Dwt2Error(st, "dwt2_forward")
+        raise Dwt2Error(st, name)
     return out
+
+
+def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
+            workspace=None, stream=None, arithmetic="auto", tile_rows=0):
+    """Forward DWT of a (H, W) float32 device tensor; returns the Mallat layout."""
+    def call(y, opt, ws, nws):
+        return dwt2_forward(wavelet, levels, img.shape[1], img.shape[0], img.data_ptr(),
+                            img.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
+                            nws, _stream_handle(stream))
+    return _transform("dwt2_forward", call, img, wavelet, levels, norm, scheme, out, workspace,
+                      arithmetic, tile_rows)
 
 
 def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
-            workspace=None, stream=None, arithmetic="auto"):
+            workspace=None, stream=None, arithmetic="auto", tile_rows=0):
     """Inverse DWT of a (H, W) Mallat-layout float32 device tensor; returns the image."""
-    import torch
-    _check_image(coef)
-    h, w = coef.shape
-    if out is None:
-        out = torch.empty((h, w), dtype=torch.float32, device=coef.device)
-    _check_image(out)
-    opt = make_options(norm, scheme, arithmetic)
-    ws, nws = _workspace(wavelet, levels, w, h, opt, coef.device, workspace)
-    st = dwt2_inverse(wavelet, levels, w, h, coef.data_ptr(), coef.stride(0), out.data_ptr(),
-                      out.stride(0), EXT_WHOLE_SYMMETRIC, opt,
-                      ws.data_ptr() if ws is not None else None, nws, _stream_handle(stream))
+    def call(y, opt, ws, nws):
+        return dwt2_inverse(wavelet, levels, coef.shape[1], coef.shape[0], coef.data_ptr(),
+                            coef.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
+                            nws, _stream_handle(stream))
+    return _transform("dwt2_inverse", call, coef, wavelet, levels, norm, scheme, out, workspace,
+                      arithmetic, tile_rows)
+
+
+def autotune(x, wavelet="cdf53", levels=1, inverse=False, norm="unit_dc", repeats=20, out=None,
+             workspace=None, stream=None):
+    """dwt2_autotune: the forward (or inverse) transform of x, as forward() (or
+    inverse()) computes it, timing every built tile height at every level and
+    recording the fastest in the process-wide table.  Blocks until done."""
+    def call(y, opt, ws, nws):
+        return dwt2_autotune(inverse, wavelet, levels, x.shape[1], x.shape[0], x.data_ptr(),
+                             x.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
+                             nws, repeats, _stream_handle(stream))
+    return _transform("dwt2_autotune", call, x, wavelet, levels, norm, "auto", out, workspace,
+                      "auto", 0)
+
+
+def tile_rows(wavelet, width, height, inverse=False, norm="unit_dc", arithmetic="auto",
+              rows=0) -> int:
+    """Tile height a call with these options uses for one width x height level."""
+    st, r = dwt2_tile_rows(inverse, wavelet, width, height,
+                           make_options(norm, "auto", arithmetic, rows))
     if st != OK:
-        raise Dwt2Error(st, "dwt2_inverse")
-    return out
+        raise Dwt2Error(st, "dwt2_tile_rows")
+    return r
+
+
+def save_tuning(path, arch=None):
+    """Write the tuned table to a JSON file, tagged with the GPU architecture
+    (that of device 0 unless given)."""
+    import json
+    st, text = dwt2_tune_export()
+    if st != OK:
+        raise Dwt2Error(st, "dwt2_tune_export")
+    if arch is None:
+        import torch
+        arch = torch.cuda.get_device_properties(0).gcnArchName
+    entries = [dict(zip(("wavelet", "inverse", "width", "height", "rows"), map(int, l.split())))
+               for l in text.splitlines()]
+    with open(path, "w") as f:
+        json.dump({"arch": arch, "entries": entries}, f, indent=1)
+
+
+def load_tuning(path, arch=None) -> int:
+    """Add the entries of a save_tuning file to the table; a file tuned on
+    another architecture is refused (ValueError).  Returns the entry count."""
+    import json
+    with open(path) as f:
+        d = json.load(f)
+    if arch is None:
+        import torch
+        arch = torch.cuda.get_device_properties(0).gcnArchName
+    if d.get("arch") != arch:
+        raise ValueError(f"tuning for {d.get('arch')!r}, this device is {arch!r}")
+    text = "".join(f"{e['wavelet']} {e['inverse']} {e['width']} {e['height']} {e['rows']}\n"
+                   for e in d["entries"])
+    st = dwt2_tune_import(text)
+    if st != OK:
+        raise Dwt2Error(st, "dwt2_tune_import")
+    return len(d["entries"])
 
 
 class Batch:

@@ -17,7 +17,7 @@ import subprocess
 
 import pytest
 
-from paper_1605_00561_amd import build
+from paper_1605_00561_amd import build, dwt2
 from scheme_model import read_table1
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -72,10 +72,15 @@ def test_tile_kernels_have_table1_barriers(counts, direction):
 
 @pytest.mark.parametrize("direction", ["forward", "inverse"])
 def test_fused_kernels_have_two_barriers_per_pair(counts, direction):
+    """Every built tile height, FP32 and FP64: the barrier count does not
+    depend on the height (rows per wavefront only widen each step)."""
     for wid, wav in WAVELET_IDS.items():
-        for t in ("float", "double"):
-            n = _find(counts, rf"k_fused_{direction}<{wid}, {t}>")
-            assert n == 2 * TABLE1[(wav, "monolithic*")][0], (direction, wav, t)
+        built = [(r, "float") for r in dwt2.TILE_ROWS[wav]] + [(dwt2.TILE_ROWS_FP64[wav], "double")]
+        for rows, t in built:
+            n = _find(counts, rf"k_fused_{direction}<{wid}, {rows}, {t}>")
+            assert n == 2 * TABLE1[(wav, "monolithic*")][0], (direction, wav, rows, t)
+        kernels = [k for k in counts if re.search(rf"k_fused_{direction}<{wid}, ", k)]
+        assert len(kernels) == len(built), kernels
 
 
 def test_rowcol_kernels_have_no_barriers(counts):

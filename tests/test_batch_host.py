@@ -91,10 +91,13 @@ def test_options_errors():
     a, n = images(img())
     for opt, status in [(dict(scheme="sweldens"), dwt2.E_UNSUPPORTED),
                         (dict(scheme="rowcol"), dwt2.E_UNSUPPORTED),
-                        (dict(scheme="monolithic*-tile"), dwt2.E_UNSUPPORTED)]:
+                        (dict(scheme="monolithic*-tile"), dwt2.E_UNSUPPORTED),
+                        # batches run at their own tile height; tile_rows must be 0
+                        (dict(tile_rows=3), dwt2.E_UNSUPPORTED),
+                        (dict(tile_rows=4), dwt2.E_UNSUPPORTED)]:
         assert both(a, n, opt=dwt2.make_options(**opt)) == [status] * 2
     o = dwt2.make_options()
-    o.reserved[4] = 1
+    o.reserved[3] = 1
     assert both(a, n, opt=o) == [dwt2.E_ARG] * 2
     o = dwt2.make_options()
     o.norm = 9
@@ -130,9 +133,9 @@ def test_alias_errors():
     assert both(a, n) == [dwt2.E_ALIAS] * 2
 
 
-# The fused kernel's tile: 64 x 16 quadruples including a halo of one
-# quadruple per side for 5/3.
-TILE_QW, TILE_QH = 64, 16
+# The batched 5/3 tile: 64 x 12 quadruples (3 rows per wavefront) including
+# a halo of one quadruple per side.
+TILE_QW, TILE_QH = 64, 12
 
 
 def test_tile_total_overflow_is_an_argument_error():

@@ -1,0 +1,98 @@
+"""GPU tests of the fused kernel's tile heights and of dwt2_autotune (through
+the C ABI).
+
+Every built height must give bitwise the coefficients (and samples) of the
+automatic choice, in both directions, for all wavelets, at sizes that span
+several centring cells and end in ragged tiles; the automatic choice is held
+to the oracle by the parity tests, and again here on the same inputs.
+dwt2_autotune must leave in dst exactly what the plain call gives and record
+only built heights.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1605_00561_amd import workloads as wl
+from test_gpu_parity import check, dev, empty_dev, exact_expected, to_dev, to_host
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1605_00561_amd import dwt2  # noqa: E402
+
+WAVELETS = ["cdf53", "cdf97", "dd137"]
+# (width, height, levels, pitch): several 18..30-row cells per level, odd
+# sizes, a pitched buffer, a tall narrow image.
+CASES = [(300, 500, 3, None), (1030, 770, 2, 1040), (77, 45, 3, None), (129, 1201, 4, None),
+         (2, 2, 1, None), (5, 7, 2, None)]
+
+
+@pytest.fixture(autouse=True)
+def empty_table():
+    dwt2.dwt2_tune_reset()
+    yield
+    dwt2.dwt2_tune_reset()
+
+
+@pytest.mark.parametrize("norm", ["unit_dc", "paper"])
+@pytest.mark.parametrize("wav", WAVELETS)
+def test_every_height_gives_the_same_bits(wav, norm):
+    rng = np.random.default_rng(400)
+    for (w, h, lev, pitch) in CASES:
+        x = rng.integers(0, 256, size=(h, w)).astype(np.float32)
+        xd = to_dev(x, pitch)
+        base = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch))
+        back = dwt2.inverse(base, wav, lev, norm, out=empty_dev(h, w, pitch))
+        what = f"{wav} {norm} {w}x{h} L{lev}"
+        for rows in dwt2.TILE_ROWS[wav]:
+            y = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows)
+            z = dwt2.inverse(base, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows)
+            torch.cuda.synchronize()
+            assert torch.equal(y, base), f"forward {what} rows {rows}"
+            assert torch.equal(z, back), f"inverse {what} rows {rows}"
+        if norm == "unit_dc":
+            got = to_host(base)
+            check(got, oracle.forward(x.astype(np.float64), wav, lev, norm),
+                  exact_expected(wav, lev, norm), "fwd " + what)
+            check(to_host(back), oracle.inverse(got, wav, lev, norm),
+                  exact_expected(wav, lev, norm), "inv " + what)
+
+
+def test_every_height_at_8192():
+    """The headline level (8192^2, 9/7) at every height: identical bits."""
+    x = to_dev(wl.workload_image("cdf97_8192_l1"))
+    base = dwt2.forward(x, "cdf97", 1)
+    back = dwt2.inverse(base, "cdf97", 1)
+    for rows in dwt2.TILE_ROWS["cdf97"]:
+        assert torch.equal(dwt2.forward(x, "cdf97", 1, tile_rows=rows), base), rows
+        assert torch.equal(dwt2.inverse(base, "cdf97", 1, tile_rows=rows), back), rows
+
+
+@pytest.mark.parametrize("wav", WAVELETS)
+def test_autotune_leaves_the_plain_result_and_records_built_heights(wav):
+    rng = np.random.default_rng(401)
+    w, h, lev = 1500, 900, 4
+    x = to_dev(rng.integers(0, 256, size=(h, w)).astype(np.float32))
+    want = dwt2.forward(x, wav, lev)
+    got = dwt2.autotune(x, wav, lev, repeats=3, out=empty_dev(h, w))
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    want_inv = dwt2.inverse(want, wav, lev)
+    got_inv = dwt2.autotune(want, wav, lev, inverse=True, repeats=3, out=empty_dev(h, w))
+    torch.cuda.synchronize()
+    assert torch.equal(got_inv, want_inv)
+    st, text = dwt2.dwt2_tune_export()
+    assert st == dwt2.OK
+    entries = [tuple(map(int, line.split())) for line in text.splitlines()]
+    sizes, (cw, ch) = [], (w, h)
+    for _ in range(lev):
+        sizes.append((cw, ch))
+        cw, ch = (cw + 1) // 2, (ch + 1) // 2
+    wid = dwt2.WAVELETS[wav]
+    assert sorted(e[:4] for e in entries) == sorted((wid, d, a, b) for d in (0, 1) for (a, b) in sizes)
+    for (_, d, a, b, rows) in entries:
+        assert rows in dwt2.TILE_ROWS[wav]
+        assert dwt2.tile_rows(wav, a, b, inverse=bool(d)) == rows
+    # calls now run at the tuned heights and still give the same bits
+    assert torch.equal(dwt2.forward(x, wav, lev), want)
+    assert torch.equal(dwt2.inverse(want, wav, lev), want_inv)
