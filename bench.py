@@ -330,10 +330,11 @@ def _median_us(torch, fn, reps):
     return statistics.median(a.elapsed_time(b) for a, b in ev) * 1e3
 
 
-def _graph_us(torch, fn, n=20, reps=5):
+def _graph_us(torch, fn, n=20, reps=5, warm=3):
     """Device time per call of fn, from a HIP graph of n back-to-back calls
     (host launch overhead excluded; what remains is the kernels and the gaps
-    between graph nodes).  Median over reps replays."""
+    between graph nodes).  Median over reps replays, after `warm` untimed
+    replays (the first launches after an idle host gap run slower)."""
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -345,7 +346,8 @@ def _graph_us(torch, fn, n=20, reps=5):
         for _ in range(n):
             fn()
     stream = torch.cuda.current_stream()
-    g.replay()
+    for _ in range(warm):
+        g.replay()
     ts = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

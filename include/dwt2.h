@@ -52,6 +52,17 @@ extern "C" {
 
 #define DWT2_VERSION 3
 
+/*
+ * The enums below have int as their underlying type in C++ as well as in C,
+ * so any int a caller passes for one of them is a value of that type and is
+ * answered with a status code (DWT2_E_UNSUPPORTED for unknown values).
+ */
+#ifdef __cplusplus
+#define DWT2_ENUM(name) enum name : int
+#else
+#define DWT2_ENUM(name) enum name
+#endif
+
 /* Status codes. */
 #define DWT2_OK 0
 #define DWT2_E_ARG (-1)         /* null pointer, non-positive size, pitch < width, bad levels */
@@ -63,7 +74,7 @@ extern "C" {
 #define DWT2_E_STATE (-7)       /* server stopping, or unknown / already collected ticket */
 
 /* Wavelets (Sec. 5, "Evaluation"). */
-typedef enum dwt2_wavelet {
+typedef DWT2_ENUM(dwt2_wavelet) {
     DWT2_CDF53 = 0, /* P = -1/2 (1 + z^-1), U = 1/4 (1 + z): one lifting pair */
     DWT2_CDF97 = 1, /* two lifting pairs alpha, beta, gamma, delta */
     DWT2_DD137 = 2  /* (4,4) Deslauriers-Dubuc: P = 1/16 (z + z^-2) - 9/16 (1 + z^-1),
@@ -71,7 +82,7 @@ typedef enum dwt2_wavelet {
 } dwt2_wavelet;
 
 /* Boundary extension.  Only whole-sample symmetric is implemented. */
-typedef enum dwt2_ext { DWT2_EXT_WHOLE_SYMMETRIC = 0 } dwt2_ext;
+typedef DWT2_ENUM(dwt2_ext) { DWT2_EXT_WHOLE_SYMMETRIC = 0 } dwt2_ext;
 
 /*
  * Normalisation, applied once per 2-D level to LL and HH (HL and LH have
@@ -82,7 +93,7 @@ typedef enum dwt2_ext { DWT2_EXT_WHOLE_SYMMETRIC = 0 } dwt2_ext;
  * and DD 13/7: no scaling; 9/7: LL / K^2, HH * K^2 with K = 1.23017410491...).  Per level k the two differ by exact powers of two:
  * PAPER = UNIT_DC * 2^(k-1) * {2 for LL, 1 for HL and LH, 1/2 for HH}.
  */
-typedef enum dwt2_norm { DWT2_NORM_UNIT_DC = 0, DWT2_NORM_PAPER = 1 } dwt2_norm;
+typedef DWT2_ENUM(dwt2_norm) { DWT2_NORM_UNIT_DC = 0, DWT2_NORM_PAPER = 1 } dwt2_norm;
 
 /*
  * Scheme of the per-level kernel.  All give the same coefficients up to FP32
@@ -108,7 +119,7 @@ typedef enum dwt2_norm { DWT2_NORM_UNIT_DC = 0, DWT2_NORM_PAPER = 1 } dwt2_norm;
  *   POLYPHASE_STAR        scalar P0 parts, then N_{P1,U1} as one step, then
  *                         scalar U0 parts (Sec. 4): 1 barrier per pair.
  */
-typedef enum dwt2_scheme {
+typedef DWT2_ENUM(dwt2_scheme) {
     DWT2_SCHEME_AUTO = 0,
     DWT2_SCHEME_MONOLITHIC_STAR = 1,
     DWT2_SCHEME_SWELDENS = 2,
@@ -128,7 +139,7 @@ typedef enum dwt2_scheme {
  * MONOLITHIC_STAR kernel in double precision (other schemes: FP32 only,
  * DWT2_E_UNSUPPORTED).  AUTO selects FP32.
  */
-typedef enum dwt2_arith { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_ARITH_FP64 = 2 } dwt2_arith;
+typedef DWT2_ENUM(dwt2_arith) { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_ARITH_FP64 = 2 } dwt2_arith;
 
 /*
  * Tile height of the fused MONOLITHIC_STAR kernel.  A work-group lifts one
