@@ -330,11 +330,12 @@ def _median_us(torch, fn, reps):
     return statistics.median(a.elapsed_time(b) for a, b in ev) * 1e3
 
 
-def _graph_us(torch, fn, n=20, reps=5, warm=3):
+def _graph_us(torch, fn, n=20, reps=5, warm_s=0.03):
     """Device time per call of fn, from a HIP graph of n back-to-back calls
     (host launch overhead excluded; what remains is the kernels and the gaps
-    between graph nodes).  Median over reps replays, after `warm` untimed
-    replays (the first launches after an idle host gap run slower)."""
+    between graph nodes).  Median over reps replays, after untimed replays
+    for at least warm_s seconds: kernels launched right after the idle gap
+    of a graph capture were measured ~3 % slower."""
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -346,8 +347,12 @@ def _graph_us(torch, fn, n=20, reps=5, warm=3):
         for _ in range(n):
             fn()
     stream = torch.cuda.current_stream()
-    for _ in range(warm):
+    t_warm = time.perf_counter()
+    while True:
         g.replay()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t_warm >= warm_s:
+            break
     ts = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
