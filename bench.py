@@ -208,7 +208,7 @@ def main():
 
     fwd_mean = statistics.fmean(fwd_ms)
     achieved = BYTES_PER_PX * npx / (fwd_mean * 1e-3) / 1e9
-    kernel = f"k_fused_forward<{wcode}, {dwt2.tile_rows(wav, W, H)}, float>"
+    kernel = f"k_fused_forward<{wcode}, {dwt2.tile_rows(wav, W, H)}, float, 2>"
     traffic = traffic_from_profiles("fused_forward_cdf97_8192", kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -291,12 +291,14 @@ def tile_table(dwt2, torch, x, y, z, reps, sizes=(8192, 2048, 512)):
 def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
     """Device time of one level per scheme (HIP-graph timed, as _graph_us)."""
     table = {}
-    for name in ("monolithic*", "monolithic*:fp64", "monolithic*-tile", "monolithic", "sweldens",
+    for name in ("monolithic*", "monolithic*:fp64", "monolithic*:1buf", "monolithic*-tile",
+                 "monolithic", "sweldens",
                  "iwahashi", "iwahashi*", "explosive", "explosive*", "polyphase*", "rowcol",
                  "monolithic*@cdf53", "monolithic*@dd137"):
         name_w, _, wname = name.partition("@")
-        scheme, _, arith = name_w.partition(":")
-        arith = arith or "auto"
+        scheme, _, variant = name_w.partition(":")
+        arith = "fp64" if variant == "fp64" else "auto"
+        nb = 1 if variant == "1buf" else 0
         wav_ = wname or wav
         ws = None
         st, nbytes = dwt2.dwt2_workspace_bytes(wav_, lev, xs[0].shape[1], xs[0].shape[0],
@@ -308,7 +310,7 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
             f = dwt2.forward if direction == "forward" else dwt2.inverse
             src, dst = (xs[0], ys[0]) if direction == "forward" else (ys[0], zs[0])
             us = _graph_us(torch, lambda: f(src, wav_, lev, scheme=scheme, out=dst, workspace=ws,
-                                            arithmetic=arith), reps=reps)
+                                            arithmetic=arith, lds_buffers=nb), reps=reps)
             gbs = BYTES_PER_PX * npx / (us * 1e-6) / 1e9
             res[direction] = {"us": round(us, 2), "Gpixel_s": round(npx / (us * 1e-6) / 1e9, 1),
                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}

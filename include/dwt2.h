@@ -157,13 +157,27 @@ typedef DWT2_ENUM(dwt2_arith) { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_A
  * returns DWT2_E_UNSUPPORTED.
  */
 
-/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO, 0). */
+/*
+ * LDS buffering of the fused MONOLITHIC_STAR kernel (Sec. 6 and Table 2).
+ * Each spatial step publishes the two components it reads across rows to
+ * LDS planes.  Double buffering (2, the default) gives the predict and update
+ * steps separate planes, so one barrier per step suffices: a step's planes are
+ * rewritten two steps later, after the next step's barrier.  Single buffering
+ * (1) overwrites one set of planes in place, adding a barrier between a step's
+ * reads and the next publication (2 barriers per step, half the LDS).  Both
+ * give bitwise identical results.  0 selects 2.  1 with FP64 arithmetic,
+ * another value, or a nonzero value with another scheme or with the batched
+ * calls returns DWT2_E_UNSUPPORTED.
+ */
+
+/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO, 0, 0). */
 typedef struct dwt2_options {
     int norm;        /* dwt2_norm */
     int scheme;      /* dwt2_scheme */
     int arithmetic;  /* dwt2_arith */
     int tile_rows;   /* fused-kernel tile height (above); 0 = automatic */
-    int reserved[4]; /* must be zero */
+    int lds_buffers; /* fused-kernel LDS buffering (above); 0 = double */
+    int reserved[3]; /* must be zero */
 } dwt2_options;
 
 /*
@@ -344,7 +358,7 @@ int dwt2_server_destroy(dwt2_server *server);
  * holds at most 4096 entries, further sizes are not recorded).  Later calls
  * with tile_rows == 0 use the recorded height of a level of that exact size.
  * Argument rules are those of dwt2_forward; the scheme must be AUTO or
- * MONOLITHIC_STAR, the arithmetic AUTO or FP32 and tile_rows 0, else
+ * MONOLITHIC_STAR, the arithmetic AUTO or FP32, tile_rows and lds_buffers 0, else
  * DWT2_E_UNSUPPORTED; repeats must be in [1, 1000], else DWT2_E_ARG.  The
  * call blocks until its work on `stream` is done and must not be captured in
  * a graph.  The table is locked internally: any thread may call any function.

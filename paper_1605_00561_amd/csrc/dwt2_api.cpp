@@ -34,6 +34,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Config {
     int wavelet, norm, scheme, arithmetic, tile_rows;
+    int lds_buffers;  // 0 = default (2)
 };
 
 int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c)
@@ -46,6 +47,7 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     c->scheme = DWT2_SCHEME_AUTO;
     c->arithmetic = DWT2_ARITH_AUTO;
     c->tile_rows = 0;
+    c->lds_buffers = 0;
     if (opt) {
         for (int r : opt->reserved)
             if (r != 0) return DWT2_E_ARG;
@@ -53,6 +55,7 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
         c->scheme = opt->scheme;
         c->arithmetic = opt->arithmetic;
         c->tile_rows = opt->tile_rows;
+        c->lds_buffers = opt->lds_buffers;
     }
     if (c->arithmetic < DWT2_ARITH_AUTO || c->arithmetic > DWT2_ARITH_FP64) return DWT2_E_UNSUPPORTED;
     if (c->norm != DWT2_NORM_UNIT_DC && c->norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
@@ -69,8 +72,15 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
         (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR ||
          !dwt2::fused_rows_supported(c->wavelet, c->arithmetic == DWT2_ARITH_FP64, c->tile_rows)))
         return DWT2_E_UNSUPPORTED;
+    // Single-buffered planes: fused kernel, FP32 lifting only.
+    if (c->lds_buffers != 0 &&
+        (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR || (c->lds_buffers != 1 && c->lds_buffers != 2) ||
+         (c->lds_buffers == 1 && c->arithmetic == DWT2_ARITH_FP64)))
+        return DWT2_E_UNSUPPORTED;
     return DWT2_OK;
 }
+
+int buffers_of(const Config &c) { return c.lds_buffers == 0 ? 2 : c.lds_buffers; }
 
 // ---------------------------------------------------------------------------
 // Tile height of the fused kernel per level.  Tuned entries, keyed by
@@ -328,7 +338,8 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
             e = dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
             e = dwt2::launch_fused_forward(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
-                                           choose_rows(c.cfg, false, a.W, a.H), a, stream);
+                                           choose_rows(c.cfg, false, a.W, a.H), buffers_of(c.cfg), a,
+                                           stream);
         else
             e = dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
         if (e != hipSuccess) return hip_status(e);
@@ -354,7 +365,8 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
             e = dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
             e = dwt2::launch_fused_inverse(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
-                                           choose_rows(c.cfg, true, a.W, a.H), a, stream);
+                                           choose_rows(c.cfg, true, a.W, a.H), buffers_of(c.cfg), a,
+                                           stream);
         else
             e = dwt2::launch_tile_inverse(c.cfg.wavelet, c.cfg.scheme, a, stream);
         if (e != hipSuccess) return hip_status(e);
@@ -410,7 +422,8 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
     if (count < 0 || count > DWT2_BATCH_MAX || (count > 0 && !images)) return DWT2_E_ARG;
     int st = parse(DWT2_CDF53, ext, opt, &p->cfg);
     if (st != DWT2_OK) return st;
-    if (p->cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || p->cfg.tile_rows != 0) return DWT2_E_UNSUPPORTED;
+    if (p->cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || p->cfg.tile_rows != 0 || p->cfg.lds_buffers != 0)
+        return DWT2_E_UNSUPPORTED;
     p->rec.resize(count);
     p->buf_off[0].resize(count);
     p->buf_off[1].resize(count);
@@ -564,9 +577,9 @@ int time_level(bool inverse, const Checked &c, const void *args, int rows, int r
                hipEvent_t e0, hipEvent_t e1, hipStream_t stream, float *ms)
 {
     auto run = [&]() {
-        return inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows,
+        return inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg),
                                                     *(const dwt2::InvArgs *)args, stream)
-                       : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows,
+                       : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg),
                                                     *(const dwt2::FwdArgs *)args, stream);
     };
     hipError_t e = hipEventRecord(e0, stream);
@@ -656,7 +669,7 @@ DWT2_EXPORT int dwt2_autotune(int inverse, dwt2_wavelet wavelet, int levels, int
                         workspace, workspace_bytes, &c);
     if (st != DWT2_OK) return st;
     if (c.cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || c.cfg.arithmetic != DWT2_ARITH_FP32 ||
-        c.cfg.tile_rows != 0)
+        c.cfg.tile_rows != 0 || c.cfg.lds_buffers != 0)
         return DWT2_E_UNSUPPORTED;
     if (repeats < 1 || repeats > 1000) return DWT2_E_ARG;
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -135,8 +135,12 @@ constexpr int kFusedRowsMax = 3;
 constexpr int kFusedRows[3][kFusedRowsMax] = {{2, 3, 0}, {2, 3, 4}, {3, 6, 0}};
 constexpr int kFusedRowsFp64[3] = {3, 4, 6};
 bool fused_rows_supported(int wavelet, bool fp64, int rows);
-hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, const FwdArgs &a, hipStream_t s);
-hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, const InvArgs &a, hipStream_t s);
+// buffers: 2 = double-buffered LDS planes (one barrier per spatial step), 1 =
+// single-buffered (two per step; FP32 only).
+hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, int buffers, const FwdArgs &a,
+                                hipStream_t s);
+hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, int buffers, const InvArgs &a,
+                                hipStream_t s);
 // Tiles of the fused kernel for one W x H level at `rows` (0 when a side is
 // below 2 or the height is not built).
 long long fused_tile_count(int wavelet, int rows, int W, int H);

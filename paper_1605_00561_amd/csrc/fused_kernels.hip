@@ -72,8 +72,10 @@ struct Geo {
     static constexpr int HQ = Halo<WAV>::HQ, PAD = Halo<WAV>::PAD, CELL = Halo<WAV>::CELL;
     static constexpr int TY = NW * RB, IX = TX - 2 * HQ, IY = TY - 2 * HQ;
     static constexpr int PLANE_ROWS = TY + 2 * PAD;
-    // Elements of the two plane buffers (two components each).
-    static constexpr int PLANE_ELEMS = 2 * 2 * PLANE_ROWS * TX;
+    // Elements of NB plane buffers (two components each).
+    template <int NB>
+    static constexpr int plane_elems() { return NB * 2 * PLANE_ROWS * TX; }
+    static constexpr int PLANE_ELEMS = plane_elems<2>();
     static_assert(IY > 0 && CELL % IY == 0, "a tile's output rows must lie in one centring cell");
     // Quadruple row whose mean centres tile row tr (before mirroring).
     __device__ static int centre_row(int tr) { return tr * IY / CELL * CELL + CELL / 2; }
@@ -136,14 +138,16 @@ __device__ __forceinline__ int xcd_tile(int ntiles)
 }
 
 // Row planes in LDS: [buffer][component][tile row + PAD][lane]; the PAD rows
-// above and below the tile are read only by halo rows.
-template <int WAV, int RB, typename T>
+// above and below the tile are read only by halo rows.  NB = 2: the predict
+// step uses buffer 0 and the update step buffer 1 (double buffering); NB = 1:
+// both use the one buffer (single buffering, an extra barrier per step).
+template <int WAV, int RB, typename T, int NB>
 struct Planes {
     T *base;
     __device__ __forceinline__ T &at(int b, int comp, int r, int c) const
     {
         using G = Geo<WAV, RB>;
-        return base[((b * 2 + comp) * G::PLANE_ROWS + r + G::PAD) * TX + c];
+        return base[(((NB == 1 ? 0 : b) * 2 + comp) * G::PLANE_ROWS + r + G::PAD) * TX + c];
     }
 };
 
@@ -202,9 +206,9 @@ struct Across {
     template <int D>
     __device__ __forceinline__ T get() const { return lane_shift<D>(v); }
 };
-template <int WAV, int RB, typename T>
+template <int WAV, int RB, typename T, int NB>
 struct Down {
-    const Planes<WAV, RB, T> &pl;
+    const Planes<WAV, RB, T, NB> &pl;
     int b, comp, r, lane;
     template <int D>
     __device__ __forceinline__ T get() const { return pl.at(b, comp, r + D, lane); }
@@ -216,14 +220,14 @@ struct Down {
 // buffer 0, published before the barrier); P1 P1* LL is P1 applied to the
 // vertical sum.  All reads are of pre-step values.  The inverse reads the
 // post-step values and subtracts, except the P1 P1* term, which keeps its sign.
-template <int WAV, bool INV, int RB, typename T>
-__device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane, int k)
+template <int WAV, bool INV, int RB, typename T, int NB>
+__device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, RB, T, NB> &pl, int w, int lane, int k)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
         const int r = tile_row(j, w);
-        const T vll = taps<WAV, true>((T)0, k, Down<WAV, RB, T>{pl, 0, 0, r, lane});
-        const T vhl = taps<WAV, true>((T)0, k, Down<WAV, RB, T>{pl, 0, 1, r, lane});
+        const T vll = taps<WAV, true>((T)0, k, Down<WAV, RB, T, NB>{pl, 0, 0, r, lane});
+        const T vhl = taps<WAV, true>((T)0, k, Down<WAV, RB, T, NB>{pl, 0, 1, r, lane});
         const T hll = taps<WAV, true>((T)0, k, Across<T>{q[j][LL]});
         const T hlh = taps<WAV, true>((T)0, k, Across<T>{q[j][LH]});
         const T dll = taps<WAV, true>((T)0, k, Across<T>{vll});
@@ -242,14 +246,14 @@ __device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, RB
 // Neighbour part of an update step, S_{U1} (inverse: S_{-U1}), on every row:
 //   LL += U1 HL + U1* LH + U1 U1* HH;  HL += U1* HH;  LH += U1 HH
 // with the rows of plane buffer 1.
-template <int WAV, bool INV, int RB, typename T>
-__device__ __forceinline__ void update_step(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane, int k)
+template <int WAV, bool INV, int RB, typename T, int NB>
+__device__ __forceinline__ void update_step(T (&q)[RB][4], const Planes<WAV, RB, T, NB> &pl, int w, int lane, int k)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
         const int r = tile_row(j, w);
-        const T vlh = taps<WAV, false>((T)0, k, Down<WAV, RB, T>{pl, 1, 0, r, lane});
-        const T vhh = taps<WAV, false>((T)0, k, Down<WAV, RB, T>{pl, 1, 1, r, lane});
+        const T vlh = taps<WAV, false>((T)0, k, Down<WAV, RB, T, NB>{pl, 1, 0, r, lane});
+        const T vhh = taps<WAV, false>((T)0, k, Down<WAV, RB, T, NB>{pl, 1, 1, r, lane});
         const T hhl = taps<WAV, false>((T)0, k, Across<T>{q[j][HL]});
         const T hhh = taps<WAV, false>((T)0, k, Across<T>{q[j][HH]});
         const T dhh = taps<WAV, false>((T)0, k, Across<T>{vhh});
@@ -267,8 +271,8 @@ __device__ __forceinline__ void update_step(T (&q)[RB][4], const Planes<WAV, RB,
 
 // The components a step reads across rows: LL, HL for the predict (buffer
 // 0), LH, HH for the update (buffer 1).
-template <int WAV, int RB, typename T>
-__device__ __forceinline__ void publish_predict(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane)
+template <int WAV, int RB, typename T, int NB>
+__device__ __forceinline__ void publish_predict(T (&q)[RB][4], const Planes<WAV, RB, T, NB> &pl, int w, int lane)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
@@ -276,8 +280,8 @@ __device__ __forceinline__ void publish_predict(T (&q)[RB][4], const Planes<WAV,
         pl.at(0, 1, tile_row(j, w), lane) = q[j][HL];
     }
 }
-template <int WAV, int RB, typename T>
-__device__ __forceinline__ void publish_update(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane)
+template <int WAV, int RB, typename T, int NB>
+__device__ __forceinline__ void publish_update(T (&q)[RB][4], const Planes<WAV, RB, T, NB> &pl, int w, int lane)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
@@ -331,16 +335,22 @@ __device__ __forceinline__ void scalar_unpredict(T (&q)[RB][4], T p)
     }
 }
 
-template <int WAV, int RB, typename T>
-__device__ __forceinline__ void forward_tile(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane)
+// Double buffering (NB = 2) needs one barrier per spatial step: a step's
+// planes are rewritten only two steps later, after the next step's barrier.
+// Single buffering (NB = 1) adds one between a step's reads and the next
+// publication (Sec. 6: 2 barriers per step instead of 1).
+template <int WAV, int RB, typename T, int NB>
+__device__ __forceinline__ void forward_tile(T (&q)[RB][4], const Planes<WAV, RB, T, NB> &pl, int w, int lane)
 {
     using C = Coef<WAV, T>;
 #pragma unroll
     for (int k = 0; k < Lift<WAV>::K; k++) {
+        if (NB == 1 && k > 0) __syncthreads();
         publish_predict(q, pl, w, lane);
         __syncthreads();
         predict_step<WAV, false>(q, pl, w, lane, k);
         scalar_predict(q, C::p(k));
+        if (NB == 1) __syncthreads();
         publish_update(q, pl, w, lane);
         __syncthreads();
         update_step<WAV, false>(q, pl, w, lane, k);
@@ -348,18 +358,20 @@ __device__ __forceinline__ void forward_tile(T (&q)[RB][4], const Planes<WAV, RB
     }
 }
 
-template <int WAV, int RB, typename T>
-__device__ __forceinline__ void inverse_tile(T (&q)[RB][4], const Planes<WAV, RB, T> &pl, int w, int lane)
+template <int WAV, int RB, typename T, int NB>
+__device__ __forceinline__ void inverse_tile(T (&q)[RB][4], const Planes<WAV, RB, T, NB> &pl, int w, int lane)
 {
     using C = Coef<WAV, T>;
 #pragma unroll
     for (int kk = 0; kk < Lift<WAV>::K; kk++) {
         const int k = Lift<WAV>::K - 1 - kk;
         scalar_unupdate(q, C::u(k));
+        if (NB == 1 && kk > 0) __syncthreads();
         publish_update(q, pl, w, lane);
         __syncthreads();
         update_step<WAV, true>(q, pl, w, lane, k);
         scalar_unpredict(q, C::p(k));
+        if (NB == 1) __syncthreads();
         publish_predict(q, pl, w, lane);
         __syncthreads();
         predict_step<WAV, true>(q, pl, w, lane, k);
@@ -373,12 +385,12 @@ __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)
 
 // Horizontal fast path: the tile's 128 pixel columns lie inside the image and
 // rows are 8-byte aligned, so each pixel-row pair is one float2 per lane.
-template <int WAV, int RB, typename T, bool VEC>
+template <int WAV, int RB, typename T, bool VEC, int NB = 2>
 __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int tr, int w, int lane)
 {
     using G = Geo<WAV, RB>;
     constexpr int HQ = G::HQ, TY = G::TY, IX = G::IX, IY = G::IY;
-    const Planes<WAV, RB, T> pl{lds};
+    const Planes<WAV, RB, T, NB> pl{lds};
     const int W = a.W, H = a.H;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1, WH = W >> 1, HHr = H >> 1;
     const int qc = tc * IX - HQ + lane;
@@ -432,12 +444,12 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int t
     }
 }
 
-template <int WAV, int RB, typename T, bool VEC>
+template <int WAV, int RB, typename T, bool VEC, int NB = 2>
 __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int tr, int w, int lane)
 {
     using G = Geo<WAV, RB>;
     constexpr int HQ = G::HQ, TY = G::TY, IX = G::IX, IY = G::IY;
-    const Planes<WAV, RB, T> pl{lds};
+    const Planes<WAV, RB, T, NB> pl{lds};
     const int W = a.W, H = a.H;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1;
     const int qc = tc * IX - HQ + lane;
@@ -501,11 +513,11 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int t
     }
 }
 
-template <int WAV, int RB, typename T>
+template <int WAV, int RB, typename T, int NB>
 __global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, int ntiles)
 {
     constexpr int HQ = Halo<WAV>::HQ;
-    __shared__ T sm[Geo<WAV, RB>::PLANE_ELEMS];
+    __shared__ T sm[Geo<WAV, RB>::template plane_elems<NB>()];
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;  // uniform over the work-group
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
@@ -514,16 +526,16 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, 
     const bool vec = px_first >= 0 && px_first + 2 * TX <= a.W &&
                      (((uintptr_t)a.in | (uintptr_t)(a.in_pitch * 4)) & 7) == 0;
     if (vec)
-        fwd_body<WAV, RB, T, true>(a, sm, tc, tr, w, lane);
+        fwd_body<WAV, RB, T, true, NB>(a, sm, tc, tr, w, lane);
     else
-        fwd_body<WAV, RB, T, false>(a, sm, tc, tr, w, lane);
+        fwd_body<WAV, RB, T, false, NB>(a, sm, tc, tr, w, lane);
 }
 
-template <int WAV, int RB, typename T>
+template <int WAV, int RB, typename T, int NB>
 __global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, int ntiles)
 {
     constexpr int HQ = Halo<WAV>::HQ;
-    __shared__ T sm[Geo<WAV, RB>::PLANE_ELEMS];
+    __shared__ T sm[Geo<WAV, RB>::template plane_elems<NB>()];
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
@@ -532,9 +544,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, 
     const bool vec = px_first >= 0 && px_first + 2 * TX <= a.W &&
                      (((uintptr_t)a.out | (uintptr_t)(a.out_pitch * 4)) & 7) == 0;
     if (vec)
-        inv_body<WAV, RB, T, true>(a, sm, tc, tr, w, lane);
+        inv_body<WAV, RB, T, true, NB>(a, sm, tc, tr, w, lane);
     else
-        inv_body<WAV, RB, T, false>(a, sm, tc, tr, w, lane);
+        inv_body<WAV, RB, T, false, NB>(a, sm, tc, tr, w, lane);
 }
 
 // Batched levels.  A work-group finds its image by a search over the tile
@@ -694,32 +706,35 @@ Grid fused_grid(int W, int H)
     return g;
 }
 
-// FP64 kernels are built at one height per wavelet.
+// FP64 kernels are built at one height per wavelet and double-buffered;
+// FP32 kernels at every height, single- and double-buffered.
 template <int WAV, int RB>
-hipError_t fused_fwd(bool fp64, const FwdArgs &a, hipStream_t s)
+hipError_t fused_fwd(bool fp64, bool single, const FwdArgs &a, hipStream_t s)
 {
     const Grid g = fused_grid<WAV, RB>(a.W, a.H);
     const dim3 grid(g.blocks), block(NTHREADS);
     if constexpr (RB == kFusedRowsFp64[WAV])
-        if (fp64) return launch(k_fused_forward<WAV, RB, double>, grid, block, s, a, g.ntx, g.ntiles);
+        if (fp64 && !single) return launch(k_fused_forward<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles);
     if (fp64) return hipErrorInvalidValue;
-    return launch(k_fused_forward<WAV, RB, float>, grid, block, s, a, g.ntx, g.ntiles);
+    return single ? launch(k_fused_forward<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles)
+                  : launch(k_fused_forward<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles);
 }
 
 template <int WAV, int RB>
-hipError_t fused_inv(bool fp64, const InvArgs &a, hipStream_t s)
+hipError_t fused_inv(bool fp64, bool single, const InvArgs &a, hipStream_t s)
 {
     const Grid g = fused_grid<WAV, RB>(a.W, a.H);
     const dim3 grid(g.blocks), block(NTHREADS);
     if constexpr (RB == kFusedRowsFp64[WAV])
-        if (fp64) return launch(k_fused_inverse<WAV, RB, double>, grid, block, s, a, g.ntx, g.ntiles);
+        if (fp64 && !single) return launch(k_fused_inverse<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles);
     if (fp64) return hipErrorInvalidValue;
-    return launch(k_fused_inverse<WAV, RB, float>, grid, block, s, a, g.ntx, g.ntiles);
+    return single ? launch(k_fused_inverse<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles)
+                  : launch(k_fused_inverse<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles);
 }
 
 // The launcher of (wavelet, rows), over the built heights.
 template <bool INV, int WAV, int I = 0>
-hipError_t dispatch_rows(int rows, bool fp64, const void *args, hipStream_t s)
+hipError_t dispatch_rows(int rows, bool fp64, bool single, const void *args, hipStream_t s)
 {
     if constexpr (I == kFusedRowsMax) {
         return hipErrorInvalidValue;
@@ -727,21 +742,24 @@ hipError_t dispatch_rows(int rows, bool fp64, const void *args, hipStream_t s)
         constexpr int RB = kFusedRows[WAV][I];
         if constexpr (RB > 0) {
             if (rows == RB)
-                return INV ? fused_inv<WAV, RB>(fp64, *(const InvArgs *)args, s)
-                           : fused_fwd<WAV, RB>(fp64, *(const FwdArgs *)args, s);
+                return INV ? fused_inv<WAV, RB>(fp64, single, *(const InvArgs *)args, s)
+                           : fused_fwd<WAV, RB>(fp64, single, *(const FwdArgs *)args, s);
         }
-        return dispatch_rows<INV, WAV, I + 1>(rows, fp64, args, s);
+        return dispatch_rows<INV, WAV, I + 1>(rows, fp64, single, args, s);
     }
 }
 
 template <bool INV>
-hipError_t dispatch(int wavelet, bool fp64, int rows, const void *args, hipStream_t s)
+hipError_t dispatch(int wavelet, bool fp64, int rows, int buffers, const void *args, hipStream_t s)
 {
-    if (!fused_rows_supported(wavelet, fp64, rows)) return hipErrorInvalidValue;
+    if (!fused_rows_supported(wavelet, fp64, rows) || (buffers != 1 && buffers != 2) ||
+        (fp64 && buffers != 2))
+        return hipErrorInvalidValue;
+    const bool single = buffers == 1;
     switch (wavelet) {
-    case CDF53: return dispatch_rows<INV, CDF53>(rows, fp64, args, s);
-    case CDF97: return dispatch_rows<INV, CDF97>(rows, fp64, args, s);
-    case DD137: return dispatch_rows<INV, DD137>(rows, fp64, args, s);
+    case CDF53: return dispatch_rows<INV, CDF53>(rows, fp64, single, args, s);
+    case CDF97: return dispatch_rows<INV, CDF97>(rows, fp64, single, args, s);
+    case DD137: return dispatch_rows<INV, DD137>(rows, fp64, single, args, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -774,14 +792,16 @@ bool fused_rows_supported(int wavelet, bool fp64, int rows)
     return false;
 }
 
-hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, const FwdArgs &a, hipStream_t s)
+hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, int buffers, const FwdArgs &a,
+                                hipStream_t s)
 {
-    return dispatch<false>(wavelet, fp64, rows, &a, s);
+    return dispatch<false>(wavelet, fp64, rows, buffers, &a, s);
 }
 
-hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, const InvArgs &a, hipStream_t s)
+hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, int buffers, const InvArgs &a,
+                                hipStream_t s)
 {
-    return dispatch<true>(wavelet, fp64, rows, &a, s);
+    return dispatch<true>(wavelet, fp64, rows, buffers, &a, s);
 }
 
 long long fused_tile_count(int wavelet, int rows, int W, int H)

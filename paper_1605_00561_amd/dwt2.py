@@ -53,7 +53,8 @@ ARITHS = {"auto": ARITH_AUTO, "fp32": ARITH_FP32, "fp64": ARITH_FP64,
 
 class Options(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_int), ("scheme", ctypes.c_int), ("arithmetic", ctypes.c_int),
-                ("tile_rows", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("tile_rows", ctypes.c_int), ("lds_buffers", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class Image(ctypes.Structure):
@@ -150,12 +151,14 @@ def library() -> ctypes.CDLL:
     return _lib
 
 
-def make_options(norm="unit_dc", scheme="auto", arithmetic="auto", tile_rows=0) -> Options:
+def make_options(norm="unit_dc", scheme="auto", arithmetic="auto", tile_rows=0,
+                 lds_buffers=0) -> Options:
     o = Options()
     o.norm = NORMS[norm]
     o.scheme = SCHEMES[scheme]
     o.arithmetic = ARITHS[arithmetic]
     o.tile_rows = int(tile_rows)
+    o.lds_buffers = int(lds_buffers)
     return o
 
 
@@ -325,7 +328,7 @@ def _stream_handle(stream):
 
 
 def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, arithmetic,
-               tile_rows):
+               tile_rows, lds_buffers=0):
     """Allocate out / workspace as needed and run call(opt, ws, ws_bytes) -> status,
     a closure over the C entry point with the tensors' pointers."""
     import torch
@@ -334,7 +337,7 @@ def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, ari
     if out is None:
         out = torch.empty((h, w), dtype=torch.float32, device=x.device)
     _check_image(out)
-    opt = make_options(norm, scheme, arithmetic, tile_rows)
+    opt = make_options(norm, scheme, arithmetic, tile_rows, lds_buffers)
     ws, nws = _workspace(wavelet, levels, w, h, opt, x.device, workspace)
     st = call(out, opt, ws.data_ptr() if ws is not None else None, nws)
     if st != OK:
@@ -343,25 +346,25 @@ def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, ari
 
 
 def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
-            workspace=None, stream=None, arithmetic="auto", tile_rows=0):
+            workspace=None, stream=None, arithmetic="auto", tile_rows=0, lds_buffers=0):
     """Forward DWT of a (H, W) float32 device tensor; returns the Mallat layout."""
     def call(y, opt, ws, nws):
         return dwt2_forward(wavelet, levels, img.shape[1], img.shape[0], img.data_ptr(),
                             img.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                             nws, _stream_handle(stream))
     return _transform("dwt2_forward", call, img, wavelet, levels, norm, scheme, out, workspace,
-                      arithmetic, tile_rows)
+                      arithmetic, tile_rows, lds_buffers)
 
 
 def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
-            workspace=None, stream=None, arithmetic="auto", tile_rows=0):
+            workspace=None, stream=None, arithmetic="auto", tile_rows=0, lds_buffers=0):
     """Inverse DWT of a (H, W) Mallat-layout float32 device tensor; returns the image."""
     def call(y, opt, ws, nws):
         return dwt2_inverse(wavelet, levels, coef.shape[1], coef.shape[0], coef.data_ptr(),
                             coef.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                             nws, _stream_handle(stream))
     return _transform("dwt2_inverse", call, coef, wavelet, levels, norm, scheme, out, workspace,
-                      arithmetic, tile_rows)
+                      arithmetic, tile_rows, lds_buffers)
 
 
 def autotune(x, wavelet="cdf53", levels=1, inverse=False, norm="unit_dc", repeats=20, out=None,

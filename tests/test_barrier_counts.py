@@ -72,13 +72,18 @@ def test_tile_kernels_have_table1_barriers(counts, direction):
 
 @pytest.mark.parametrize("direction", ["forward", "inverse"])
 def test_fused_kernels_have_two_barriers_per_pair(counts, direction):
-    """Every built tile height, FP32 and FP64: the barrier count does not
-    depend on the height (rows per wavefront only widen each step)."""
+    """Every built tile height, FP32 and FP64, double-buffered: Table 1's count
+    (the height only widens each step).  Single-buffered (FP32): one more
+    barrier per spatial step, except before the first publication."""
     for wid, wav in WAVELET_IDS.items():
-        built = [(r, "float") for r in dwt2.TILE_ROWS[wav]] + [(dwt2.TILE_ROWS_FP64[wav], "double")]
-        for rows, t in built:
-            n = _find(counts, rf"k_fused_{direction}<{wid}, {rows}, {t}>")
-            assert n == 2 * TABLE1[(wav, "monolithic*")][0], (direction, wav, rows, t)
+        table1 = TABLE1[(wav, "monolithic*")][0]
+        built = [(r, "float", 2) for r in dwt2.TILE_ROWS[wav]] + \
+                [(r, "float", 1) for r in dwt2.TILE_ROWS[wav]] + \
+                [(dwt2.TILE_ROWS_FP64[wav], "double", 2)]
+        for rows, t, nb in built:
+            n = _find(counts, rf"k_fused_{direction}<{wid}, {rows}, {t}, {nb}>")
+            per_body = table1 if nb == 2 else 2 * table1 - 1
+            assert n == 2 * per_body, (direction, wav, rows, t, nb)
         kernels = [k for k in counts if re.search(rf"k_fused_{direction}<{wid}, ", k)]
         assert len(kernels) == len(built), kernels
 

@@ -94,10 +94,11 @@ def test_options_errors():
                         (dict(scheme="monolithic*-tile"), dwt2.E_UNSUPPORTED),
                         # batches run at their own tile height; tile_rows must be 0
                         (dict(tile_rows=3), dwt2.E_UNSUPPORTED),
-                        (dict(tile_rows=4), dwt2.E_UNSUPPORTED)]:
+                        (dict(tile_rows=4), dwt2.E_UNSUPPORTED),
+                        (dict(lds_buffers=1), dwt2.E_UNSUPPORTED)]:
         assert both(a, n, opt=dwt2.make_options(**opt)) == [status] * 2
     o = dwt2.make_options()
-    o.reserved[3] = 1
+    o.reserved[2] = 1
     assert both(a, n, opt=o) == [dwt2.E_ARG] * 2
     o = dwt2.make_options()
     o.norm = 9

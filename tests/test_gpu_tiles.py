@@ -45,11 +45,14 @@ def test_every_height_gives_the_same_bits(wav, norm):
         back = dwt2.inverse(base, wav, lev, norm, out=empty_dev(h, w, pitch))
         what = f"{wav} {norm} {w}x{h} L{lev}"
         for rows in dwt2.TILE_ROWS[wav]:
-            y = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows)
-            z = dwt2.inverse(base, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows)
-            torch.cuda.synchronize()
-            assert torch.equal(y, base), f"forward {what} rows {rows}"
-            assert torch.equal(z, back), f"inverse {what} rows {rows}"
+            for nb in (1, 2):  # single- and double-buffered LDS planes
+                y = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows,
+                                 lds_buffers=nb)
+                z = dwt2.inverse(base, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows,
+                                 lds_buffers=nb)
+                torch.cuda.synchronize()
+                assert torch.equal(y, base), f"forward {what} rows {rows} buffers {nb}"
+                assert torch.equal(z, back), f"inverse {what} rows {rows} buffers {nb}"
         if norm == "unit_dc":
             got = to_host(base)
             check(got, oracle.forward(x.astype(np.float64), wav, lev, norm),
@@ -64,8 +67,9 @@ def test_every_height_at_8192():
     base = dwt2.forward(x, "cdf97", 1)
     back = dwt2.inverse(base, "cdf97", 1)
     for rows in dwt2.TILE_ROWS["cdf97"]:
-        assert torch.equal(dwt2.forward(x, "cdf97", 1, tile_rows=rows), base), rows
-        assert torch.equal(dwt2.inverse(base, "cdf97", 1, tile_rows=rows), back), rows
+        for nb in (1, 2):
+            assert torch.equal(dwt2.forward(x, "cdf97", 1, tile_rows=rows, lds_buffers=nb), base)
+            assert torch.equal(dwt2.inverse(base, "cdf97", 1, tile_rows=rows, lds_buffers=nb), back)
 
 
 @pytest.mark.parametrize("wav", WAVELETS)

@@ -49,6 +49,18 @@ def test_unbuilt_heights_are_rejected():
         assert _fwd(dwt2.make_options(scheme=scheme, tile_rows=3)) == dwt2.E_UNSUPPORTED
 
 
+def test_lds_buffering_option_is_validated():
+    for bad in (-1, 3, 7):
+        assert _fwd(dwt2.make_options(lds_buffers=bad)) == dwt2.E_UNSUPPORTED
+    assert _fwd(dwt2.make_options(arithmetic="fp64", lds_buffers=1)) == dwt2.E_UNSUPPORTED
+    for scheme in ("sweldens", "rowcol", "monolithic*-tile", "explosive*"):
+        assert _fwd(dwt2.make_options(scheme=scheme, lds_buffers=1)) == dwt2.E_UNSUPPORTED
+        assert _fwd(dwt2.make_options(scheme=scheme, lds_buffers=2)) == dwt2.E_UNSUPPORTED
+    o = dwt2.make_options(lds_buffers=1)
+    o.reserved[2] = 1
+    assert _fwd(o) == dwt2.E_ARG
+
+
 def tiles(wav, rows, w, h):
     hq = HALO[wav]
     qw, qh = (w + 1) // 2, (h + 1) // 2
@@ -201,6 +213,7 @@ def test_autotune_argument_errors():
         assert tune(dwt2.make_options(scheme="sweldens"), inverse=inverse) == dwt2.E_UNSUPPORTED
         assert tune(dwt2.make_options(arithmetic="fp64"), inverse=inverse) == dwt2.E_UNSUPPORTED
         assert tune(dwt2.make_options(tile_rows=4), inverse=inverse) == dwt2.E_UNSUPPORTED
+        assert tune(dwt2.make_options(lds_buffers=1), inverse=inverse) == dwt2.E_UNSUPPORTED
         assert tune(levels=2, inverse=inverse) == dwt2.E_WORKSPACE
         assert lib.dwt2_autotune(inverse, 1, 1, 16, 16, FAKE, 16, FAKE, 16, 0, None, None, 0, 5,
                                  None) == dwt2.E_ALIAS
