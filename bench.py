@@ -70,18 +70,30 @@ def parse():
     return ap.parse_args()
 
 
+def source_digest(paths) -> str:
+    """SHA-256 of C/C++/HIP sources with comments removed and whitespace
+    collapsed: it changes with the code, not with its comments."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for p in paths:
+        text = open(os.path.join(ROOT, p)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def traffic_from_profiles(tag: str, kernel: str):
     """HBM bytes per launch of the dominant kernel from the committed PMC summary
     (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when it is
-    absent, was taken on different kernel sources or of another kernel."""
+    absent, was taken on different kernel code or of another kernel."""
     path = os.path.join(ROOT, "profiles", f"{tag}_hbm_counters.json")
     if not os.path.exists(path):
         return None
     try:
-        import hashlib
         rec = json.load(open(path))
-        blob = b"".join(open(os.path.join(ROOT, s), "rb").read() for s in rec["sources"])
-        if hashlib.sha256(blob).hexdigest() != rec["sources_sha256"] or rec["kernel"] != kernel:
+        if source_digest(rec["sources"]) != rec["sources_digest"] or rec["kernel"] != kernel:
             return None
         return int(round(rec["bytes_per_launch"]))
     except (OSError, KeyError, ValueError):

@@ -8,13 +8,13 @@
 //
 // Mapping.  A work-group owns one overlapping tile of 64 x (NW * RB)
 // quadruples (HQ quadruples of halo per side), as in the paper's block-based
-// method (Sec. 6); RB, the rows per wavefront, is a template parameter with
-// a few built values per wavelet (the host picks one per level).  Lane c of wavefront w holds the
-// quadruples of column c in the tile rows w, w + NW, w + 2 NW, ... in
-// registers: the rows are interleaved across the wavefronts, so at any time
-// the work-group's loads and stores cover NW adjacent rows, which measured
-// about 9% faster than contiguous row runs per wavefront for this access
-// pattern.
+// method (Sec. 6); RB, the rows per wavefront, is a template parameter with a
+// few built values per wavelet (the host picks one per level).  Lane c of
+// wavefront w holds the quadruples of column c in the tile rows w, w + NW,
+// w + 2 NW, ... in registers: the rows are interleaved across the wavefronts,
+// so at any time the work-group's loads and stores cover NW adjacent rows,
+// which measured about 9% faster than contiguous row runs per wavefront for
+// this access pattern.
 //   * horizontal neighbours (c +- 1) are read from the adjacent lane with DPP
 //     wave shifts, which need no barrier (a wavefront runs in lockstep);
 //   * vertical neighbours (r +- 1) live in another wavefront: before each
@@ -22,7 +22,8 @@
 //     reads across rows (LL, HL for the predict; LH, HH for the update) to an
 //     LDS plane, and the barrier the scheme places before the step makes them
 //     visible.  Two plane buffers alternate between predict and update, so
-//     Monolithic* keeps its two barriers per lifting pair.
+//     Monolithic* keeps its two barriers per lifting pair (double buffering;
+//     single buffering, NB = 1, adds one barrier per step, Sec. 6).
 // LDS is at most 29 KB (FP32), so occupancy is set by registers.
 //
 // Borders: whole-sample symmetric extension, samples read from mirrored
