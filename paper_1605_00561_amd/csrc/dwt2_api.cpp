@@ -135,7 +135,8 @@ int geometry(int levels, int width, int height, int *ws, int *hs)
 }
 
 // Workspace: LL ping-pong buffers A (level-1 LL size) and B (level-2 LL
-// size) when levels > 1, plus a W x H intermediate for the row-column scheme.
+// size) when levels > 1, rows padded to ll_pitch(), plus a W x H
+// intermediate for the row-column scheme.
 struct Layout {
     size_t a_off, b_off, t_off, total;
 };
@@ -146,11 +147,11 @@ Layout layout(int scheme, int levels, const int *ws, const int *hs)
     size_t off = 0;
     if (levels >= 2) {
         L.a_off = off;
-        off += align_up(sizeof(float) * (size_t)((ws[0] + 1) / 2) * (size_t)((hs[0] + 1) / 2));
+        off += align_up(sizeof(float) * (size_t)dwt2::ll_pitch((ws[0] + 1) / 2) * (size_t)((hs[0] + 1) / 2));
     }
     if (levels >= 3) {
         L.b_off = off;
-        off += align_up(sizeof(float) * (size_t)((ws[1] + 1) / 2) * (size_t)((hs[1] + 1) / 2));
+        off += align_up(sizeof(float) * (size_t)dwt2::ll_pitch((ws[1] + 1) / 2) * (size_t)((hs[1] + 1) / 2));
     }
     if (scheme == DWT2_SCHEME_ROWCOL) {
         L.t_off = off;
@@ -232,7 +233,7 @@ int check_call(dwt2_wavelet wavelet, int levels, int width, int height, const fl
 
 // Arguments of forward level k (0-based).  Level k reads the image (k = 0)
 // or LL_k; LL_j (1-based j) lives in workspace buffer A for odd j, B for even
-// j, with pitch = its width; the last level writes LL into dst.
+// j, with pitch ll_pitch(its width); the last level writes LL into dst.
 dwt2::FwdArgs forward_level(const Checked &c, int k, const float *src, ptrdiff_t src_pitch,
                             float *dst, ptrdiff_t dst_pitch, void *workspace)
 {
@@ -241,7 +242,7 @@ dwt2::FwdArgs forward_level(const Checked &c, int k, const float *src, ptrdiff_t
     const int levels = c.levels, W = c.ws[k], H = c.hs[k];
     dwt2::FwdArgs a;
     a.in = k == 0 ? src : buf[(k - 1) & 1];
-    a.in_pitch = k == 0 ? src_pitch : (ptrdiff_t)W;
+    a.in_pitch = k == 0 ? src_pitch : dwt2::ll_pitch(W);
     a.det = dst;
     a.det_pitch = dst_pitch;
     a.W = W;
@@ -250,7 +251,7 @@ dwt2::FwdArgs forward_level(const Checked &c, int k, const float *src, ptrdiff_t
     a.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
     a.quantum = c.cfg.norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
     a.ll = k == levels - 1 ? dst : buf[k & 1];
-    a.ll_pitch = k == levels - 1 ? dst_pitch : (ptrdiff_t)((W + 1) / 2);
+    a.ll_pitch = k == levels - 1 ? dst_pitch : dwt2::ll_pitch((W + 1) / 2);
     return a;
 }
 
@@ -265,7 +266,7 @@ dwt2::InvArgs inverse_level(const Checked &c, int k, const float *src, ptrdiff_t
     const int levels = c.levels, W = c.ws[k], H = c.hs[k];
     dwt2::InvArgs a;
     a.ll = k == levels - 1 ? src : buf[k & 1];
-    a.ll_pitch = k == levels - 1 ? src_pitch : (ptrdiff_t)((W + 1) / 2);
+    a.ll_pitch = k == levels - 1 ? src_pitch : dwt2::ll_pitch((W + 1) / 2);
     a.det = src;
     a.det_pitch = src_pitch;
     a.W = W;
@@ -274,7 +275,7 @@ dwt2::InvArgs inverse_level(const Checked &c, int k, const float *src, ptrdiff_t
     a.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
     a.quantum = c.cfg.norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
     a.out = k == 0 ? dst : buf[(k - 1) & 1];
-    a.out_pitch = k == 0 ? dst_pitch : (ptrdiff_t)W;
+    a.out_pitch = k == 0 ? dst_pitch : dwt2::ll_pitch(W);
     return a;
 }
 

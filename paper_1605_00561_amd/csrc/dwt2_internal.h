@@ -66,6 +66,11 @@ struct Scale {
     float ll, hh;
 };
 
+// Row pitch (floats) of an LL buffer of width w in the library's workspace: a
+// multiple of 64 floats, so every row starts on a 256-byte boundary and the
+// kernels' 8-byte vector accesses apply whatever the width.
+__host__ __device__ __forceinline__ ptrdiff_t ll_pitch(int w) { return ((ptrdiff_t)w + 63) & ~(ptrdiff_t)63; }
+
 // Whole-sample symmetric extension: index j -> [0, n), period 2(n-1), n >= 2.
 __host__ __device__ __forceinline__ int ws_mirror(int j, int n)
 {

@@ -626,9 +626,9 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_forward(BatchLevel b)
     const int W = level_size(im.W, k), H = level_size(im.H, k);
     FwdArgs a;
     a.in = k == 0 ? im.src : im.buf[(k - 1) & 1];
-    a.in_pitch = k == 0 ? im.src_pitch : (ptrdiff_t)W;
+    a.in_pitch = k == 0 ? im.src_pitch : ll_pitch(W);
     a.ll = k == last ? im.dst : im.buf[k & 1];
-    a.ll_pitch = k == last ? im.dst_pitch : (ptrdiff_t)((W + 1) / 2);
+    a.ll_pitch = k == last ? im.dst_pitch : ll_pitch((W + 1) / 2);
     a.det = im.dst;
     a.det_pitch = im.dst_pitch;
     a.W = W;
@@ -655,11 +655,11 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_inverse(BatchLevel b)
     const int W = level_size(im.W, k), H = level_size(im.H, k);
     InvArgs a;
     a.ll = k == last ? im.src : im.buf[k & 1];
-    a.ll_pitch = k == last ? im.src_pitch : (ptrdiff_t)((W + 1) / 2);
+    a.ll_pitch = k == last ? im.src_pitch : ll_pitch((W + 1) / 2);
     a.det = im.src;
     a.det_pitch = im.src_pitch;
     a.out = k == 0 ? im.dst : im.buf[(k - 1) & 1];
-    a.out_pitch = k == 0 ? im.dst_pitch : (ptrdiff_t)W;
+    a.out_pitch = k == 0 ? im.dst_pitch : ll_pitch(W);
     a.W = W;
     a.H = H;
     a.inv_s = b.s[im.wavelet];

@@ -55,13 +55,20 @@ def _al(n):
     return (n + 255) // 256 * 256
 
 
+def _p(w):
+    """Row pitch of a workspace LL buffer: the width rounded up to 64 floats."""
+    return (w + 63) // 64 * 64
+
+
 def test_workspace_bytes():
     assert _ws("cdf53", 1, 512, 512) == 0
     assert _ws("cdf97", 1, 8192, 8192) == 0
-    assert _ws("cdf97", 2, 100, 60) == _al(4 * 50 * 30)
-    assert _ws("cdf53", 5, 101, 61) == _al(4 * 51 * 31) + _al(4 * 26 * 16)
+    assert _ws("cdf97", 2, 100, 60) == _al(4 * _p(50) * 30)
+    assert _ws("cdf53", 5, 101, 61) == _al(4 * _p(51) * 31) + _al(4 * _p(26) * 16)
+    assert _ws("cdf53", 3, 8192, 8192) == 4 * 4096 * 4096 + 4 * 2048 * 2048
     assert _ws("cdf53", 1, 100, 60, "rowcol") == _al(4 * 100 * 60)
-    assert _ws("cdf97", 3, 100, 60, "rowcol") == _al(4 * 50 * 30) + _al(4 * 25 * 15) + _al(4 * 6000)
+    assert _ws("cdf97", 3, 100, 60, "rowcol") == \
+        _al(4 * _p(50) * 30) + _al(4 * _p(25) * 15) + _al(4 * 6000)
     st, _ = dwt2.dwt2_workspace_bytes("cdf53", 1, 1, 8, None)
     assert st == dwt2.E_SIZE
     n = ctypes.c_size_t()
