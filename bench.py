@@ -142,8 +142,8 @@ class HipTimer:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
-              file=sys.stderr)
+        print(f"bench.py: the transform runs on one GPU per process; --gpus {args.gpus} is not "
+              "supported (several GPUs would each take whole images or row bands)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
