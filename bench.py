@@ -306,7 +306,7 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
     for name in ("monolithic*", "monolithic*:fp64", "monolithic*:1buf", "monolithic*-tile",
                  "monolithic", "sweldens",
                  "iwahashi", "iwahashi*", "explosive", "explosive*", "polyphase*", "rowcol",
-                 "monolithic*@cdf53", "monolithic*@dd137"):
+                 "monolithic*@cdf53", "sweldens@cdf53", "monolithic*@dd137"):
         name_w, _, wname = name.partition("@")
         scheme, _, variant = name_w.partition(":")
         arith = "fp64" if variant == "fp64" else "auto"
