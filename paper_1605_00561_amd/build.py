@@ -26,7 +26,7 @@ ARCH = os.environ.get("DWT2_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["dwt2_api.cpp", "dwt2_server.cpp", "tile_kernels.hip", "fused_kernels.hip",
            "rowcol_kernels.hip"]
-HEADERS = ["dwt2_internal.h"]
+HEADERS = ["dwt2_internal.h", "server_plan.h"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

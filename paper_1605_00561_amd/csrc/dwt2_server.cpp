@@ -29,6 +29,7 @@
 
 #include "../../include/dwt2.h"
 #include "dwt2_internal.h"
+#include "server_plan.h"
 
 #define DWT2_EXPORT extern "C" __attribute__((visibility("default")))
 
@@ -47,76 +48,8 @@ size_t span_bytes(ptrdiff_t pitch, int w, int h)
     return sizeof(float) * ((size_t)(h - 1) * (size_t)pitch + (size_t)w);
 }
 
-// Disjoint byte ranges; insert merges, so a query only needs the range that
-// starts last before the queried end.
-class RangeSet {
-    std::map<uintptr_t, uintptr_t> r_;  // lo -> hi
-
-public:
-    bool overlaps(uintptr_t lo, uintptr_t hi) const
-    {
-        auto it = r_.lower_bound(hi);
-        if (it == r_.begin()) return false;
-        --it;
-        return it->second > lo;
-    }
-    void insert(uintptr_t lo, uintptr_t hi)
-    {
-        auto it = r_.lower_bound(lo);
-        if (it != r_.begin() && std::prev(it)->second >= lo) {
-            --it;
-            lo = it->first;
-        }
-        while (it != r_.end() && it->first <= hi) {
-            hi = std::max(hi, it->second);
-            it = r_.erase(it);
-        }
-        r_[lo] = hi;
-    }
-    void clear() { r_.clear(); }
-};
-
-// First-fit free list over [0, size) in 256-byte units.
-class Arena {
-    std::map<size_t, size_t> free_;  // offset -> bytes
-
-public:
-    explicit Arena(size_t size) { free_[0] = size; }
-    bool fits(size_t bytes) const
-    {
-        for (const auto &f : free_)
-            if (f.second >= bytes) return true;
-        return false;
-    }
-    size_t alloc(size_t bytes)  // caller checked fits()
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            const size_t off = it->first, rest = it->second - bytes;
-            free_.erase(it);
-            if (rest) free_[off + bytes] = rest;
-            return off;
-        }
-        return SIZE_MAX;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        if (!bytes) return;
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
+using dwt2::serve::Arena;
+using dwt2::serve::Group;
 
 struct Pending {
     unsigned long long ticket;
@@ -134,12 +67,7 @@ struct Flight {
     size_t off = 0, bytes = 0;
 };
 
-// Workspace of one direction's group: table + the images' LL buffers.
-struct Group {
-    int count = 0, lmax = 0;
-    size_t ll = 0;
-    size_t bytes() const { return count ? dwt2::batch_table_bytes(count, lmax) + ll : 0; }
-};
+size_t table_bytes(int count, int lmax) { return dwt2::batch_table_bytes(count, lmax); }
 
 }  // namespace
 
@@ -180,25 +108,14 @@ void dwt2_server::schedule()
 
         // Take the longest admissible prefix of the pending queue.
         Group g[2];
-        RangeSet written, read;
-        size_t n = 0;
-        for (; n < pending.size() && (int)n < max_batch; n++) {
-            const Pending &p = pending[n];
+        auto item = [&](size_t i) {
+            const Pending &p = pending[i];
             const uintptr_t s0 = (uintptr_t)p.r.src, d0 = (uintptr_t)p.r.dst;
-            const uintptr_t s1 = s0 + span_bytes(p.r.src_pitch, p.r.width, p.r.height);
-            const uintptr_t d1 = d0 + span_bytes(p.r.dst_pitch, p.r.width, p.r.height);
-            if (written.overlaps(s0, s1) || written.overlaps(d0, d1) || read.overlaps(d0, d1)) break;
-            Group t[2] = {g[0], g[1]};
-            Group &k = t[p.r.inverse ? 1 : 0];
-            k.count++;
-            k.lmax = std::max(k.lmax, p.r.levels);
-            k.ll += p.ll_bytes;
-            if (!space.fits(t[0].bytes() + t[1].bytes())) break;
-            g[0] = t[0];
-            g[1] = t[1];
-            written.insert(d0, d1);
-            read.insert(s0, s1);
-        }
+            return dwt2::serve::Item{s0, s0 + span_bytes(p.r.src_pitch, p.r.width, p.r.height), d0,
+                                     d0 + span_bytes(p.r.dst_pitch, p.r.width, p.r.height),
+                                     p.r.inverse, p.r.levels, p.ll_bytes};
+        };
+        const size_t n = dwt2::serve::next_batch(item, pending.size(), max_batch, space, table_bytes, g);
         if (n == 0) {
             if (inflight.empty()) {
                 // Unreachable: submission rejects a request larger than the
@@ -215,7 +132,7 @@ void dwt2_server::schedule()
             continue;
         }
         Flight f;
-        f.bytes = g[0].bytes() + g[1].bytes();
+        f.bytes = group_bytes(g[0], table_bytes) + group_bytes(g[1], table_bytes);
         f.off = space.alloc(f.bytes);
         std::vector<Pending> take(pending.begin(), pending.begin() + n);
         pending.erase(pending.begin(), pending.begin() + n);
@@ -245,7 +162,7 @@ void dwt2_server::schedule()
         char *ws = arena + f.off;
         for (int d = 0; d < 2; d++) {
             if (img[d].empty()) continue;
-            const size_t b = g[d].bytes();
+            const size_t b = group_bytes(g[d], table_bytes);
             const int st = d ? dwt2_inverse_batch(img[d].data(), (int)img[d].size(),
                                                   DWT2_EXT_WHOLE_SYMMETRIC, &opt, ws, b, stream)
                              : dwt2_forward_batch(img[d].data(), (int)img[d].size(),
