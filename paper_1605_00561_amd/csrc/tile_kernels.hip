@@ -10,12 +10,16 @@
 // one barrier:
 //
 //   Monolithic*  (Sec. 4)  T_{P1}+T^H_{P0}+T^V_{P0} | S_{U1}+S^H_{U0}+S^V_{U0}
-//   (this tile form; the default fused kernel is the streaming one)
+//   (this tile form; the default fused kernel keeps its tile in registers
+//   and moves horizontal neighbours by DPP)
 //                          2 barriers per pair, 6 LDS cells per quadruple
 //   Sweldens     (Sec. 2)  T^H_P | T^V_P | S^H_U | S^V_U
 //                          4 barriers per pair, 4 LDS cells
 //   Iwahashi     (Sec. 2)  T^I_P | R^I_{P,U} | S^I_U
 //                          3 barriers per pair, 6 LDS cells
+// and the paper's other schemes, each with Table 1's barriers: Monolithic
+// (unsplit, Sec. 3), Explosive and Explosive* (Sec. 3-4), Iwahashi* and
+// Polyphase* (Sec. 4); their steps are described where they are defined.
 //
 // Operators in the L = x[2n] phase (see dwt2_internal.h): for a component
 // X at quadruple (r, c), P X = p (X + X[r][c+1]), P* X = p (X + X[r+1][c]),
