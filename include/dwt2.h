@@ -275,7 +275,10 @@ int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext ext,
  *
  * Ordering: requests whose buffers overlap (one writes what another reads or
  * writes) never share a batch, and batches run in submission order on the
- * stream, so a request may consume an earlier request's output.
+ * stream, so a request may consume an earlier request's output.  Within a
+ * batch the forward and the inverse group run concurrently: the inverse group
+ * on a second stream the server creates, forked from the caller's stream
+ * (after its earlier work) and joined back into it (before its later work).
  * Each request gets exactly the result of dwt2_forward / dwt2_inverse with
  * the server's options.  The arena, and every request's src and dst, are
  * owned by the caller and must stay valid until the request completes.

@@ -1,6 +1,6 @@
 // dwt2_server.cpp -- the serving loop of libdwt2 (declared in include/dwt2.h):
 // requests from any host thread are grouped into batched transforms
-// (continuous batching) on one stream.
+// (continuous batching) on the caller's stream.
 //
 // Threads.  A scheduler forms each batch from the pending requests, in
 // submission order, when fewer than max_inflight batches are on the stream:
@@ -8,8 +8,13 @@
 // one already taken (such a request must run after it), or at the first one
 // whose workspace does not fit the free part of the arena.  It launches the
 // forward and the inverse group of the batch (dwt2_forward_batch /
-// dwt2_inverse_batch) and records an event.  A completer waits for the
-// oldest batch's event, stamps its requests and frees its arena block.
+// dwt2_inverse_batch) and records an event.  The two groups touch disjoint
+// memory, so when a batch has both, the inverse group runs on a second
+// stream forked from the caller's stream and joined back into it: each
+// group's latency-bound deep levels overlap the other group's work, and the
+// order against earlier and later work on the caller's stream is unchanged.
+// A completer waits for the oldest batch's event, stamps its requests and
+// frees its arena block.
 //
 // The arena is a caller-owned device buffer; the server keeps only a host-side
 // free list over it (first fit, coalescing), so nothing is allocated on the
@@ -77,6 +82,8 @@ struct dwt2_server {
     char *arena = nullptr;
     size_t arena_bytes = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;              // the inverse group's stream
+    hipEvent_t fork = nullptr, join = nullptr;
     int device = 0;
 
     std::mutex m;
@@ -160,15 +167,30 @@ void dwt2_server::schedule()
         }
         f.launched = Clock::now();
         char *ws = arena + f.off;
+        const bool both = !img[0].empty() && !img[1].empty();
+        hipError_t e = hipSuccess;
+        if (both) {  // fork: the side stream starts after the caller's earlier work
+            e = hipEventRecord(fork, stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+        }
         for (int d = 0; d < 2; d++) {
             if (img[d].empty()) continue;
             const size_t b = group_bytes(g[d], table_bytes);
-            const int st = d ? dwt2_inverse_batch(img[d].data(), (int)img[d].size(),
-                                                  DWT2_EXT_WHOLE_SYMMETRIC, &opt, ws, b, stream)
-                             : dwt2_forward_batch(img[d].data(), (int)img[d].size(),
-                                                  DWT2_EXT_WHOLE_SYMMETRIC, &opt, ws, b, stream);
+            const hipStream_t st_d = both && d ? side : stream;
+            const int st = e != hipSuccess ? DWT2_E_HIP
+                           : d ? dwt2_inverse_batch(img[d].data(), (int)img[d].size(),
+                                                    DWT2_EXT_WHOLE_SYMMETRIC, &opt, ws, b, st_d)
+                               : dwt2_forward_batch(img[d].data(), (int)img[d].size(),
+                                                    DWT2_EXT_WHOLE_SYMMETRIC, &opt, ws, b, st_d);
             for (size_t i : idx[d]) f.status[i] = st;
             ws += b;
+        }
+        if (both && e == hipSuccess) {  // join: the caller's stream waits for the side stream
+            e = hipEventRecord(join, side);
+            if (e == hipSuccess) e = hipStreamWaitEvent(stream, join, 0);
+            if (e != hipSuccess)
+                for (int &st : f.status)
+                    if (st == DWT2_OK) st = DWT2_E_HIP;
         }
         if (!f.ev && hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) != hipSuccess)
             f.ev = nullptr;
@@ -277,6 +299,15 @@ DWT2_EXPORT int dwt2_server_create(const dwt2_options *opt, const dwt2_server_co
     s->space = Arena(s->arena_bytes);
     s->stream = stream;
     s->device = device;
+    if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->join, hipEventDisableTiming) != hipSuccess) {
+        if (s->join) (void)hipEventDestroy(s->join);
+        if (s->fork) (void)hipEventDestroy(s->fork);
+        if (s->side) (void)hipStreamDestroy(s->side);
+        delete s;
+        return DWT2_E_HIP;
+    }
     s->sched = std::thread([s] { s->schedule(); });
     s->compl_ = std::thread([s] { s->complete(); });
     *out = s;
@@ -355,6 +386,11 @@ DWT2_EXPORT int dwt2_server_destroy(dwt2_server *s)
     s->sched.join();
     s->compl_.join();
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+    // every batch joined the side stream into the caller's stream before its
+    // completion event, and the completer has waited for all of them
+    (void)hipEventDestroy(s->join);
+    (void)hipEventDestroy(s->fork);
+    (void)hipStreamDestroy(s->side);
     delete s;
     return DWT2_OK;
 }

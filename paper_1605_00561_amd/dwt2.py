@@ -535,14 +535,26 @@ class Server:
     def replay(self, requests, arrival_us):
         """requests: [(src, dst, wavelet, levels, inverse)]; returns the
         Completion of each, submitted at arrival_us[i] microseconds."""
+        done = self.run(self.prepare(requests, arrival_us))
+        return [done[i] for i in range(len(requests))]
+
+    def prepare(self, requests, arrival_us):
+        """Marshal a replay once (the C arrays of requests and arrival times);
+        run() then costs only the C call."""
         n = len(requests)
         arr = (Request * max(n, 1))(*[self.request(*r) for r in requests])
         t = (ctypes.c_double * max(n, 1))(*[float(a) for a in arrival_us])
+        return n, arr, t, list(requests)  # the tensors stay referenced
+
+    def run(self, prepared):
+        """dwt2_server_replay of a prepare()d replay; returns the C array of
+        Completions (indexable)."""
+        n, arr, t, _ = prepared
         done = (Completion * max(n, 1))()
         st = dwt2_server_replay(self.handle, arr, t, n, done)
         if st != OK:
             raise Dwt2Error(st, "dwt2_server_replay")
-        return [done[i] for i in range(n)]
+        return done
 
     def close(self):
         if self.handle:
