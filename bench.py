@@ -485,7 +485,7 @@ def batch_table(dwt2, torch, workloads, reps):
     out["graph_forward"] = row(_times_us(torch, gf.replay, reps))
     out["graph_inverse"] = row(_times_us(torch, gi.replay, reps))
 
-    # one call per image through the C ABI, arguments prepared beforehand
+    # one call per image through the C ABI, arguments marshalled beforehand
     stream = torch.cuda.current_stream().cuda_stream
     calls = []
     for x, y, z, wav, lev in zip(xs, ys, zs, wavs, levs):
@@ -494,14 +494,17 @@ def batch_table(dwt2, torch, workloads, reps):
         ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
         calls.append((wav, lev, w, h, x, y, z, ws, nb))
 
+    lib = dwt2.library()
+    args = {inverse: [(dwt2.WAVELETS[wav], lev, w, h, (y if inverse else x).data_ptr(), w,
+                       (z if inverse else y).data_ptr(), w, dwt2.EXT_WHOLE_SYMMETRIC, None,
+                       ws.data_ptr(), nb, stream)
+                      for (wav, lev, w, h, x, y, z, ws, nb) in calls] for inverse in (False, True)}
+
     def loop(inverse):
-        f = dwt2.dwt2_inverse if inverse else dwt2.dwt2_forward
-        for (wav, lev, w, h, x, y, z, ws, nb) in calls:
-            a, b = (y, z) if inverse else (x, y)
-            st = f(wav, lev, w, h, a.data_ptr(), w, b.data_ptr(), w, 0, None, ws.data_ptr(), nb,
-                   stream)
-            if st != dwt2.OK:
-                raise dwt2.Dwt2Error(st, "per-image call")
+        f = lib.dwt2_inverse if inverse else lib.dwt2_forward
+        status = [f(*a) for a in args[inverse]]
+        if any(st != dwt2.OK for st in status):
+            raise dwt2.Dwt2Error(next(st for st in status if st != dwt2.OK), "per-image call")
 
     out["per_image_forward"] = row(_times_us(torch, lambda: loop(False), reps))
     out["per_image_inverse"] = row(_times_us(torch, lambda: loop(True), reps))
