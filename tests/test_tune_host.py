@@ -218,3 +218,25 @@ def test_autotune_argument_errors():
         assert lib.dwt2_autotune(inverse, 1, 1, 16, 16, FAKE, 16, FAKE, 16, 0, None, None, 0, 5,
                                  None) == dwt2.E_ALIAS
     assert dwt2.dwt2_tune_export() == (dwt2.OK, "")
+
+
+def test_tuning_file_round_trip_and_architecture_check(tmp_path):
+    import json
+    assert dwt2.dwt2_tune_import("1 0 8192 8192 3\n2 1 300 200 6\n") == dwt2.OK
+    path = str(tmp_path / "tuning.json")
+    dwt2.save_tuning(path, arch="gfx950")
+    d = json.load(open(path))
+    assert d["arch"] == "gfx950"
+    assert {(e["wavelet"], e["inverse"], e["width"], e["height"], e["rows"]) for e in d["entries"]} == \
+        {(1, 0, 8192, 8192, 3), (2, 1, 300, 200, 6)}
+    assert dwt2.dwt2_tune_reset() == dwt2.OK
+    assert dwt2.load_tuning(path, arch="gfx950") == 2
+    assert dwt2.tile_rows("cdf97", 8192, 8192) == 3
+    assert dwt2.tile_rows("dd137", 300, 200, inverse=True) == 6
+    with pytest.raises(ValueError):
+        dwt2.load_tuning(path, arch="gfx942")
+    d["entries"].append({"wavelet": 1, "inverse": 0, "width": 64, "height": 64, "rows": 9})
+    json.dump(d, open(path, "w"))
+    with pytest.raises(dwt2.Dwt2Error):  # a height that is not built: the table stays as it was
+        dwt2.load_tuning(path, arch="gfx950")
+    assert dwt2.tile_rows("cdf97", 64, 64) == dwt2.tile_rows("cdf97", 64, 64, rows=2)
