@@ -65,7 +65,8 @@ extern "C" {
 
 /* Status codes. */
 #define DWT2_OK 0
-#define DWT2_E_ARG (-1)         /* null pointer, non-positive size, pitch < width, bad levels */
+#define DWT2_E_ARG (-1)         /* null pointer, non-positive size, pitch < width, an image spanning
+                                   more than 2^60 elements ((height - 1) * pitch + width), bad levels */
 #define DWT2_E_SIZE (-2)        /* some level's input is smaller than 2 x 2 */
 #define DWT2_E_UNSUPPORTED (-3) /* unknown wavelet, extension, normalisation, scheme or arithmetic */
 #define DWT2_E_WORKSPACE (-4)   /* workspace missing or smaller than dwt2_workspace_bytes() */

@@ -13,6 +13,7 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <utility>
 #include <vector>
@@ -201,6 +202,14 @@ size_t span_bytes(ptrdiff_t pitch, int w, int h)
     return sizeof(float) * ((size_t)(h - 1) * (size_t)pitch + (size_t)w);
 }
 
+// An image may span at most 2^60 elements ((h - 1) * pitch + w), which keeps
+// byte offsets and address ranges far from 64-bit wrap-around.  pitch >= w.
+bool span_fits(ptrdiff_t pitch, int w, int h)
+{
+    constexpr long long kMaxSpan = 1LL << 60;
+    return h == 1 || (long long)pitch <= (kMaxSpan - w) / (h - 1);
+}
+
 struct Checked {
     Config cfg;
     int levels;
@@ -219,6 +228,7 @@ int check_call(dwt2_wavelet wavelet, int levels, int width, int height, const fl
     c->levels = levels;
     if (!src || !dst) return DWT2_E_ARG;
     if (src_pitch < width || dst_pitch < width) return DWT2_E_ARG;
+    if (!span_fits(src_pitch, width, height) || !span_fits(dst_pitch, width, height)) return DWT2_E_ARG;
     if (((uintptr_t)src & 3) || ((uintptr_t)dst & 3)) return DWT2_E_ARG;
     c->lay = layout(c->cfg.scheme, levels, c->ws, c->hs);
     if (c->lay.total > 0 && (!workspace || workspace_bytes < c->lay.total)) return DWT2_E_WORKSPACE;
@@ -440,6 +450,8 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
         if (st != DWT2_OK) return st;
         if (!im.src || !im.dst) return DWT2_E_ARG;
         if (im.src_pitch < im.width || im.dst_pitch < im.width) return DWT2_E_ARG;
+        if (!span_fits(im.src_pitch, im.width, im.height) || !span_fits(im.dst_pitch, im.width, im.height))
+            return DWT2_E_ARG;
         if (((uintptr_t)im.src & 3) || ((uintptr_t)im.dst & 3)) return DWT2_E_ARG;
         const Layout L = layout(DWT2_SCHEME_MONOLITHIC_STAR, im.levels, ws, hs);
         p->buf_off[0][i] = img_bytes + L.a_off;
@@ -735,14 +747,10 @@ DWT2_EXPORT int dwt2_tune_import(const char *text)
         p = *nl ? nl + 1 : nl;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    size_t fresh = 0;
-    std::vector<TuneKey> seen;
+    std::set<TuneKey> fresh;
     for (const auto &kv : add)
-        if (!g_tune.count(kv.first) && std::find(seen.begin(), seen.end(), kv.first) == seen.end()) {
-            seen.push_back(kv.first);
-            fresh++;
-        }
-    if (g_tune.size() + fresh > kTuneMax) return DWT2_E_SIZE;
+        if (!g_tune.count(kv.first)) fresh.insert(kv.first);
+    if (g_tune.size() + fresh.size() > kTuneMax) return DWT2_E_SIZE;
     for (const auto &kv : add) g_tune[kv.first] = kv.second;
     g_tune_size.store(g_tune.size(), std::memory_order_release);
     return DWT2_OK;

@@ -107,6 +107,15 @@ def test_argument_errors():
     assert _fwd(opt=o) == dwt2.E_ARG
 
 
+def test_pitch_whose_span_passes_2_60_elements_is_rejected():
+    """(height - 1) * pitch + width is capped at 2^60 elements, so byte
+    offsets and address ranges cannot wrap."""
+    limit = (2 ** 60 - 16) // 15        # largest pitch for 16 rows of 16
+    assert _fwd(src_pitch=limit + 1) == dwt2.E_ARG
+    assert _fwd(dst_pitch=limit + 1) == dwt2.E_ARG
+    assert _fwd(src_pitch=2 ** 62) == dwt2.E_ARG
+
+
 def test_size_errors():
     assert _fwd(width=1, src_pitch=1, dst_pitch=1) == dwt2.E_SIZE
     assert _fwd(height=1) == dwt2.E_SIZE

@@ -68,6 +68,7 @@ def test_per_image_errors_name_the_same_status_as_single_calls():
         (img(dst=0), dwt2.E_ARG),
         (img(sp=63), dwt2.E_ARG),
         (img(dp=10), dwt2.E_ARG),
+        (img(sp=2 ** 62), dwt2.E_ARG),              # span beyond 2^60 elements
         (img(src=FAKE + 2), dwt2.E_ARG),
         (img(w=1), dwt2.E_SIZE),
         (img(lev=7, w=64, h=64), dwt2.E_SIZE),
