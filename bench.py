@@ -243,6 +243,8 @@ def main():
                    "height": H, "levels": lev, "scheme": "monolithic*",
                    "tile_rows": {"forward": dwt2.tile_rows(wav, W, H),
                                  "inverse": dwt2.tile_rows(wav, W, H, inverse=True)},
+                   "tile_order": {"forward": dwt2.tile_order(wav, W, H),
+                                  "inverse": dwt2.tile_order(wav, W, H, inverse=True)},
                    "image": "cosine gradient (period 512) + N(0, 8^2), clipped to [0, 255]",
                    "buffer_sets": NSETS},
         "device_warmup_steps": n_dev_warm,
@@ -294,8 +296,9 @@ def tile_table(dwt2, torch, x, y, z, reps, sizes=(8192, 2048, 512)):
     n = x.shape[0]
     dwt2.autotune(x, "cdf97", 1, repeats=20, out=y)
     dwt2.autotune(y, "cdf97", 1, inverse=True, repeats=20, out=z)
-    out[f"autotuned_cdf97@{n}"] = [dwt2.tile_rows("cdf97", n, n),
-                                   dwt2.tile_rows("cdf97", n, n, inverse=True)]
+    out[f"autotuned_cdf97@{n}"] = [[dwt2.tile_rows("cdf97", n, n), dwt2.tile_order("cdf97", n, n)],
+                                   [dwt2.tile_rows("cdf97", n, n, inverse=True),
+                                    dwt2.tile_order("cdf97", n, n, inverse=True)]]
     dwt2.dwt2_tune_reset()
     return out
 
@@ -382,7 +385,8 @@ def pyramid_table(dwt2, torch, workloads, reps):
     """Per-level forward and inverse of the fused kernel on the 16384^2 CDF 9/7
     five-level workload: each level's input size timed as a one-level call on
     the LL band the previous level produced (device time per call from a HIP
-    graph of back-to-back calls), plus the whole five-level call."""
+    graph of back-to-back calls) in the tile order the rule picks and in the
+    other one, plus the whole five-level call."""
     name = "cdf97_16384_l5"
     spec = workloads.WORKLOADS[name]
     W, H, wav, lev = spec["width"], spec["height"], spec["wavelet"], spec["levels"]
@@ -399,9 +403,14 @@ def pyramid_table(dwt2, torch, workloads, reps):
         back = torch.empty_like(src)
         tf = _graph_us(torch, lambda: dwt2.forward(src, wav, 1, out=dst))
         ti = _graph_us(torch, lambda: dwt2.inverse(dst, wav, 1, out=back))
+        order = [dwt2.tile_order(wav, w, h), dwt2.tile_order(wav, w, h, inverse=True)]
+        other = ["bands" if o == "runs" else "runs" for o in order]
+        of = _graph_us(torch, lambda: dwt2.forward(src, wav, 1, out=dst, tile_order=other[0]))
+        oi = _graph_us(torch, lambda: dwt2.inverse(dst, wav, 1, out=back, tile_order=other[1]))
         npx = w * h
-        levels.append({"level": k + 1, "width": w, "height": h,
+        levels.append({"level": k + 1, "width": w, "height": h, "tile_order": order,
                        "forward_us": round(tf, 2), "inverse_us": round(ti, 2),
+                       "other_order_us": [round(of, 2), round(oi, 2)],
                        "forward_Gpixel_s": round(npx / tf / 1e3, 1),
                        "inverse_Gpixel_s": round(npx / ti / 1e3, 1),
                        "forward_hbm_frac": round(BYTES_PER_PX * npx / tf / 1e3 / HBM_PEAK_GBS, 4),
@@ -410,11 +419,16 @@ def pyramid_table(dwt2, torch, workloads, reps):
         cur = dst[:h, :w]
     st, nbytes = dwt2.dwt2_workspace_bytes(wav, lev, W, H)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    tf = _median_us(torch, lambda i: dwt2.forward(x, wav, lev, out=y, workspace=ws), reps)
-    ti = _median_us(torch, lambda i: dwt2.inverse(y, wav, lev, out=z, workspace=ws), reps)
+    # Device time per five-level call, from a HIP graph as the levels above
+    # (a single eager call also counts the binding's host work before its
+    # first launch, tens of microseconds).
+    tf = _graph_us(torch, lambda: dwt2.forward(x, wav, lev, out=y, workspace=ws), n=10)
+    ti = _graph_us(torch, lambda: dwt2.inverse(y, wav, lev, out=z, workspace=ws), n=10)
+    te = _median_us(torch, lambda i: dwt2.forward(x, wav, lev, out=y, workspace=ws), reps)
     total_px = sum(l["width"] * l["height"] for l in levels)
     return {"workload": f"{name} ({W}x{H}, {wav}, {lev} levels, fused kernel)", "levels": levels,
             "five_level_forward_us": round(tf, 1), "five_level_inverse_us": round(ti, 1),
+            "five_level_forward_eager_us": round(te, 1),
             "five_level_forward_Gpixel_s": round(total_px / tf / 1e3, 1),
             "five_level_inverse_Gpixel_s": round(total_px / ti / 1e3, 1)}
 

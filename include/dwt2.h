@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define DWT2_VERSION 3
+#define DWT2_VERSION 4
 
 /*
  * The enums below have int as their underlying type in C++ as well as in C,
@@ -171,14 +171,33 @@ typedef DWT2_ENUM(dwt2_arith) { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_A
  * calls returns DWT2_E_UNSUPPORTED.
  */
 
-/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO, 0, 0). */
+/*
+ * Tile order of the fused MONOLITHIC_STAR kernel: how the chip's eight XCDs
+ * (each with its own L2) share a level's tiles.  RUNS: each XCD takes a
+ * contiguous row-major run of tiles.  BANDS: each XCD takes one eighth of the
+ * tile columns and sweeps them from the top down, so that all XCDs work on
+ * the same rows at a time.  In both, neighbouring tiles meet in one L2 and
+ * share their halo there.  Not in the paper (a single-die design); it changes
+ * speed only, never the result.  AUTO selects per level: the entry
+ * dwt2_autotune recorded, else BANDS for levels of at least 2^27 pixels and
+ * 2048 pixels width, else RUNS.  A nonzero value with another scheme or with
+ * the batched calls returns DWT2_E_UNSUPPORTED.
+ */
+typedef DWT2_ENUM(dwt2_order) {
+    DWT2_ORDER_AUTO = 0,
+    DWT2_ORDER_RUNS = 1,
+    DWT2_ORDER_BANDS = 2
+} dwt2_order;
+
+/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO, 0, 0, AUTO). */
 typedef struct dwt2_options {
     int norm;        /* dwt2_norm */
     int scheme;      /* dwt2_scheme */
     int arithmetic;  /* dwt2_arith */
     int tile_rows;   /* fused-kernel tile height (above); 0 = automatic */
     int lds_buffers; /* fused-kernel LDS buffering (above); 0 = double */
-    int reserved[3]; /* must be zero */
+    int tile_order;  /* dwt2_order (above) */
+    int reserved[2]; /* must be zero */
 } dwt2_options;
 
 /*
@@ -347,25 +366,28 @@ int dwt2_server_replay(dwt2_server *server, const dwt2_request *requests,
 int dwt2_server_destroy(dwt2_server *server);
 
 /*
- * Tile-height autotuning
- * ----------------------
+ * Tile autotuning
+ * ---------------
  * Not in the paper, which fixes one work-group size per platform (Sec. 6).
- * The tile height only trades halo re-reads against work-groups in flight
- * (see dwt2_options), so it is tuned by measurement, per level size.
+ * The tile height only trades halo re-reads against work-groups in flight,
+ * and the tile order only changes how the XCDs meet HBM (see dwt2_options),
+ * so both are tuned by measurement, per level size.
  *
  * dwt2_autotune runs the transform that dwt2_forward (inverse == 0) or
  * dwt2_inverse (inverse != 0) runs with the same arguments and leaves the same
  * result in dst.  Along the way it runs each level `repeats` times at every
- * built FP32 height (two passes), times the runs with HIP events on `stream`,
- * and records the fastest height for (wavelet, direction, level width, level
- * height) in a table shared by the process (entries are replaced; the table
- * holds at most 4096 entries, further sizes are not recorded).  Later calls
- * with tile_rows == 0 use the recorded height of a level of that exact size.
+ * built FP32 height in both tile orders (two passes), times the runs with HIP
+ * events on `stream`, and records the fastest height and order for (wavelet,
+ * direction, level width, level height) in a table shared by the process
+ * (entries are replaced; the table holds at most 4096 entries, further sizes
+ * are not recorded).  Later FP32 calls with tile_rows == 0 (tile_order ==
+ * AUTO) use the recorded height (order) of a level of that exact size.
  * Argument rules are those of dwt2_forward; the scheme must be AUTO or
- * MONOLITHIC_STAR, the arithmetic AUTO or FP32, tile_rows and lds_buffers 0, else
- * DWT2_E_UNSUPPORTED; repeats must be in [1, 1000], else DWT2_E_ARG.  The
- * call blocks until its work on `stream` is done and must not be captured in
- * a graph.  The table is locked internally: any thread may call any function.
+ * MONOLITHIC_STAR, the arithmetic AUTO or FP32, tile_rows, lds_buffers and
+ * tile_order 0, else DWT2_E_UNSUPPORTED; repeats must be in [1, 1000], else
+ * DWT2_E_ARG.  The call blocks until its work on `stream` is done and must
+ * not be captured in a graph.  The table is locked internally: any thread may
+ * call any function.
  */
 int dwt2_autotune(int inverse, dwt2_wavelet wavelet, int levels, int width, int height,
                   const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
@@ -382,8 +404,18 @@ int dwt2_tile_rows(int inverse, dwt2_wavelet wavelet, int width, int height,
                    const dwt2_options *opt, int *rows);
 
 /*
- * The table as text, one entry per line: "wavelet inverse width height rows"
- * (decimal, single spaces, '\n' after each line), in ascending key order.
+ * Tile order (DWT2_ORDER_RUNS or DWT2_ORDER_BANDS) the fused kernel uses for
+ * one width x height level of a call with these options (tile_order, the
+ * table, or the rule of dwt2_options).  Writes *order.  Statuses as
+ * dwt2_tile_rows.
+ */
+int dwt2_tile_order(int inverse, dwt2_wavelet wavelet, int width, int height,
+                    const dwt2_options *opt, int *order);
+
+/*
+ * The table as text, one entry per line: "wavelet inverse width height rows
+ * order" (decimal, single spaces, '\n' after each line; order 0 for an entry
+ * imported without one), in ascending key order.
  * Writes up to cap bytes of it plus a terminating NUL into buf (buf may be
  * NULL when cap is 0) and the full length without the NUL into *len.
  * DWT2_E_SIZE when cap <= *len (buf then holds no partial line: buf[0] is NUL
@@ -393,10 +425,11 @@ int dwt2_tune_export(char *buf, size_t cap, size_t *len);
 
 /*
  * Add the entries of text in dwt2_tune_export's format to the table
- * (replacing entries of the same key).  The whole text is checked first: a
- * malformed line, an unknown wavelet, a size below 2 or a height that is not
- * built for that wavelet leaves the table unchanged and returns DWT2_E_ARG;
- * more entries than the table holds, DWT2_E_SIZE.
+ * (replacing entries of the same key); a line may omit the order (then the
+ * rule picks it).  The whole text is checked first: a malformed line, an
+ * unknown wavelet, a size below 2, a height that is not built for that
+ * wavelet or an order other than 0, 1, 2 leaves the table unchanged and
+ * returns DWT2_E_ARG; more entries than the table holds, DWT2_E_SIZE.
  */
 int dwt2_tune_import(const char *text);
 

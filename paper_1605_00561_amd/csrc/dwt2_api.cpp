@@ -36,6 +36,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Config {
     int wavelet, norm, scheme, arithmetic, tile_rows;
     int lds_buffers;  // 0 = default (2)
+    int tile_order;   // 0 = automatic, else DWT2_ORDER_RUNS / DWT2_ORDER_BANDS
 };
 
 int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c)
@@ -49,6 +50,7 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     c->arithmetic = DWT2_ARITH_AUTO;
     c->tile_rows = 0;
     c->lds_buffers = 0;
+    c->tile_order = 0;
     if (opt) {
         for (int r : opt->reserved)
             if (r != 0) return DWT2_E_ARG;
@@ -57,6 +59,7 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
         c->arithmetic = opt->arithmetic;
         c->tile_rows = opt->tile_rows;
         c->lds_buffers = opt->lds_buffers;
+        c->tile_order = opt->tile_order;
     }
     if (c->arithmetic < DWT2_ARITH_AUTO || c->arithmetic > DWT2_ARITH_FP64) return DWT2_E_UNSUPPORTED;
     if (c->norm != DWT2_NORM_UNIT_DC && c->norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
@@ -78,16 +81,24 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
         (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR || (c->lds_buffers != 1 && c->lds_buffers != 2) ||
          (c->lds_buffers == 1 && c->arithmetic == DWT2_ARITH_FP64)))
         return DWT2_E_UNSUPPORTED;
+    if (c->tile_order != 0 &&
+        (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR ||
+         (c->tile_order != DWT2_ORDER_RUNS && c->tile_order != DWT2_ORDER_BANDS)))
+        return DWT2_E_UNSUPPORTED;
     return DWT2_OK;
 }
 
 int buffers_of(const Config &c) { return c.lds_buffers == 0 ? 2 : c.lds_buffers; }
 
 // ---------------------------------------------------------------------------
-// Tile height of the fused kernel per level.  Tuned entries, keyed by
-// (wavelet, inverse, level width, level height), live in one table per
-// process; g_tune_size lets calls skip the lock while it is empty.
+// Tile height and tile order of the fused kernel per level.  Tuned entries,
+// keyed by (wavelet, inverse, level width, level height), live in one table
+// per process; g_tune_size lets calls skip the lock while it is empty.  An
+// entry's order is 0 when it was imported without one (the rule decides).
 using TuneKey = std::array<int, 4>;
+struct TuneVal {
+    int rows, order;
+};
 constexpr size_t kTuneMax = 4096;
 // Four work-groups per compute unit (256 CUs): below this a level is short
 // of work-groups and shorter tiles win; above it taller tiles (fewer halo
@@ -95,7 +106,7 @@ constexpr size_t kTuneMax = 4096;
 constexpr long long kFillTiles = 1024;
 
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
+std::map<TuneKey, TuneVal> g_tune;
 std::atomic<size_t> g_tune_size{0};
 
 int rule_rows(int wavelet, int W, int H)
@@ -106,16 +117,44 @@ int rule_rows(int wavelet, int W, int H)
     return pick;
 }
 
+// Tile order rule: the band order from 2^27 pixels on, when the level is at
+// least 2048 pixels (16 or more tile columns, two per XCD) wide.  Measured
+// on 9/7 and 5/3 levels from 8192^2 to 16384^2: runs are faster up to about
+// 10240^2, bands from 12288^2 on (by 6-19 % in the forward direction).
+constexpr long long kBandPixels = 1LL << 27;
+constexpr int kBandMinWidth = 2048;
+
+int rule_order(int W, int H)
+{
+    return (long long)W * H >= kBandPixels && W >= kBandMinWidth ? DWT2_ORDER_BANDS : DWT2_ORDER_RUNS;
+}
+
+// The tuned entry of a level, if any.
+bool tuned(const Config &c, bool inverse, int W, int H, TuneVal *v)
+{
+    if (!g_tune_size.load(std::memory_order_acquire)) return false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey{c.wavelet, inverse ? 1 : 0, W, H});
+    if (it == g_tune.end()) return false;
+    *v = it->second;
+    return true;
+}
+
 int choose_rows(const Config &c, bool inverse, int W, int H)
 {
     if (c.arithmetic == DWT2_ARITH_FP64) return dwt2::kFusedRowsFp64[c.wavelet];
     if (c.tile_rows) return c.tile_rows;
-    if (g_tune_size.load(std::memory_order_acquire)) {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(TuneKey{c.wavelet, inverse ? 1 : 0, W, H});
-        if (it != g_tune.end()) return it->second;
-    }
+    TuneVal v;
+    if (tuned(c, inverse, W, H, &v)) return v.rows;
     return rule_rows(c.wavelet, W, H);
+}
+
+int choose_order(const Config &c, bool inverse, int W, int H)
+{
+    if (c.tile_order) return c.tile_order;
+    TuneVal v;
+    if (c.arithmetic != DWT2_ARITH_FP64 && tuned(c, inverse, W, H, &v) && v.order) return v.order;
+    return rule_order(W, H);
 }
 
 // Level k (0-based) transforms a ws[k] x hs[k] block; each must be >= 2 x 2.
@@ -349,8 +388,8 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
             e = dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
             e = dwt2::launch_fused_forward(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
-                                           choose_rows(c.cfg, false, a.W, a.H), buffers_of(c.cfg), a,
-                                           stream);
+                                           choose_rows(c.cfg, false, a.W, a.H), buffers_of(c.cfg),
+                                           choose_order(c.cfg, false, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
         if (e != hipSuccess) return hip_status(e);
@@ -376,8 +415,8 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
             e = dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
             e = dwt2::launch_fused_inverse(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
-                                           choose_rows(c.cfg, true, a.W, a.H), buffers_of(c.cfg), a,
-                                           stream);
+                                           choose_rows(c.cfg, true, a.W, a.H), buffers_of(c.cfg),
+                                           choose_order(c.cfg, true, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_inverse(c.cfg.wavelet, c.cfg.scheme, a, stream);
         if (e != hipSuccess) return hip_status(e);
@@ -433,7 +472,8 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
     if (count < 0 || count > DWT2_BATCH_MAX || (count > 0 && !images)) return DWT2_E_ARG;
     int st = parse(DWT2_CDF53, ext, opt, &p->cfg);
     if (st != DWT2_OK) return st;
-    if (p->cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || p->cfg.tile_rows != 0 || p->cfg.lds_buffers != 0)
+    if (p->cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || p->cfg.tile_rows != 0 || p->cfg.lds_buffers != 0 ||
+        p->cfg.tile_order != 0)
         return DWT2_E_UNSUPPORTED;
     p->rec.resize(count);
     p->buf_off[0].resize(count);
@@ -585,14 +625,15 @@ DWT2_EXPORT int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext
 
 namespace {
 
-// Mean time of `repeats` back-to-back launches of one level at `rows`, in ms.
-int time_level(bool inverse, const Checked &c, const void *args, int rows, int repeats,
+// Mean time of `repeats` back-to-back launches of one level at `rows` and
+// `order`, in ms.
+int time_level(bool inverse, const Checked &c, const void *args, int rows, int order, int repeats,
                hipEvent_t e0, hipEvent_t e1, hipStream_t stream, float *ms)
 {
     auto run = [&]() {
-        return inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg),
+        return inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg), order,
                                                     *(const dwt2::InvArgs *)args, stream)
-                       : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg),
+                       : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg), order,
                                                     *(const dwt2::FwdArgs *)args, stream);
     };
     hipError_t e = hipEventRecord(e0, stream);
@@ -622,32 +663,43 @@ int tune(bool inverse, const Checked &c, const float *src, ptrdiff_t src_pitch, 
             fa = forward_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
             args = &fa;
         }
-        // Two passes over the heights; each keeps its faster pass.  Every run
-        // writes the same level output, so the next level reads the result.
-        float best[dwt2::kFusedRowsMax];
+        // Two passes over every (height, order); each keeps its faster pass.
+        // Every run writes the same level output, so the next level reads the
+        // result.
+        constexpr int kOrders[2] = {DWT2_ORDER_RUNS, DWT2_ORDER_BANDS};
+        float best[dwt2::kFusedRowsMax][2];
         for (int pass = 0; pass < 2; pass++)
-            for (int i = 0; i < dwt2::kFusedRowsMax && cand[i] > 0; i++) {
-                float ms = 0.0f;
-                const int st = time_level(inverse, c, args, cand[i], repeats, e0, e1, stream, &ms);
-                if (st != DWT2_OK) return st;
-                best[i] = pass == 0 ? ms : std::min(best[i], ms);
-            }
-        int pick = 0;
-        for (int i = 1; i < dwt2::kFusedRowsMax && cand[i] > 0; i++)
-            if (best[i] < best[pick]) pick = i;
+            for (int i = 0; i < dwt2::kFusedRowsMax && cand[i] > 0; i++)
+                for (int o = 0; o < 2; o++) {
+                    float ms = 0.0f;
+                    const int st =
+                        time_level(inverse, c, args, cand[i], kOrders[o], repeats, e0, e1, stream, &ms);
+                    if (st != DWT2_OK) return st;
+                    best[i][o] = pass == 0 ? ms : std::min(best[i][o], ms);
+                }
+        int pick = 0, pick_o = 0;
+        for (int i = 0; i < dwt2::kFusedRowsMax && cand[i] > 0; i++)
+            for (int o = 0; o < 2; o++)
+                if (best[i][o] < best[pick][pick_o]) {
+                    pick = i;
+                    pick_o = o;
+                }
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const TuneKey key{c.cfg.wavelet, inverse ? 1 : 0, c.ws[k], c.hs[k]};
-        if (g_tune.size() < kTuneMax || g_tune.count(key)) g_tune[key] = cand[pick];
+        if (g_tune.size() < kTuneMax || g_tune.count(key)) g_tune[key] = TuneVal{cand[pick], kOrders[pick_o]};
         g_tune_size.store(g_tune.size(), std::memory_order_release);
     }
     return DWT2_OK;
 }
 
-// One line of the exported table: "wavelet inverse width height rows".
-bool parse_line(const char *p, const char *end, TuneKey *key, int *rows)
+// One line of the exported table: "wavelet inverse width height rows order",
+// or without the order (0: the rule decides).
+bool parse_line(const char *p, const char *end, TuneKey *key, TuneVal *val)
 {
-    long long v[5];
-    for (int i = 0; i < 5; i++) {
+    long long v[6] = {0, 0, 0, 0, 0, 0};
+    int fields = 0;
+    for (int i = 0; i < 6; i++) {
+        if (i == 5 && p == end) break;  // the order is optional
         if (i > 0) {
             if (p >= end || *p != ' ') return false;
             p++;
@@ -660,13 +712,15 @@ bool parse_line(const char *p, const char *end, TuneKey *key, int *rows)
             p++;
         }
         v[i] = x;
+        fields++;
     }
-    if (p != end) return false;
+    if (p != end || fields < 5) return false;
     const int wavelet = (int)v[0], inverse = (int)v[1], w = (int)v[2], h = (int)v[3];
     if (wavelet > DWT2_DD137 || inverse > 1 || w < 2 || h < 2) return false;
     if (!dwt2::fused_rows_supported(wavelet, false, (int)v[4])) return false;
+    if (v[5] != 0 && v[5] != DWT2_ORDER_RUNS && v[5] != DWT2_ORDER_BANDS) return false;
     *key = TuneKey{wavelet, inverse, w, h};
-    *rows = (int)v[4];
+    *val = TuneVal{(int)v[4], (int)v[5]};
     return true;
 }
 
@@ -682,7 +736,7 @@ DWT2_EXPORT int dwt2_autotune(int inverse, dwt2_wavelet wavelet, int levels, int
                         workspace, workspace_bytes, &c);
     if (st != DWT2_OK) return st;
     if (c.cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || c.cfg.arithmetic != DWT2_ARITH_FP32 ||
-        c.cfg.tile_rows != 0 || c.cfg.lds_buffers != 0)
+        c.cfg.tile_rows != 0 || c.cfg.lds_buffers != 0 || c.cfg.tile_order != 0)
         return DWT2_E_UNSUPPORTED;
     if (repeats < 1 || repeats > 1000) return DWT2_E_ARG;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -711,6 +765,20 @@ DWT2_EXPORT int dwt2_tile_rows(int inverse, dwt2_wavelet wavelet, int width, int
     return DWT2_OK;
 }
 
+DWT2_EXPORT int dwt2_tile_order(int inverse, dwt2_wavelet wavelet, int width, int height,
+                                const dwt2_options *opt, int *order)
+{
+    if (!order) return DWT2_E_ARG;
+    Config cfg;
+    int st = parse(wavelet, DWT2_EXT_WHOLE_SYMMETRIC, opt, &cfg);
+    if (st != DWT2_OK) return st;
+    if (cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR) return DWT2_E_UNSUPPORTED;
+    if (width < 1 || height < 1) return DWT2_E_ARG;
+    if (width < 2 || height < 2 || (long long)width * height > kMaxPixels) return DWT2_E_SIZE;
+    *order = choose_order(cfg, inverse != 0, width, height);
+    return DWT2_OK;
+}
+
 DWT2_EXPORT int dwt2_tune_export(char *buf, size_t cap, size_t *len)
 {
     if (!len || (cap > 0 && !buf)) return DWT2_E_ARG;
@@ -720,7 +788,8 @@ DWT2_EXPORT int dwt2_tune_export(char *buf, size_t cap, size_t *len)
         for (const auto &kv : g_tune) {
             const TuneKey &k = kv.first;
             text += std::to_string(k[0]) + ' ' + std::to_string(k[1]) + ' ' + std::to_string(k[2]) +
-                    ' ' + std::to_string(k[3]) + ' ' + std::to_string(kv.second) + '\n';
+                    ' ' + std::to_string(k[3]) + ' ' + std::to_string(kv.second.rows) + ' ' +
+                    std::to_string(kv.second.order) + '\n';
         }
     }
     *len = text.size();
@@ -736,14 +805,14 @@ DWT2_EXPORT int dwt2_tune_export(char *buf, size_t cap, size_t *len)
 DWT2_EXPORT int dwt2_tune_import(const char *text)
 {
     if (!text) return DWT2_E_ARG;
-    std::vector<std::pair<TuneKey, int>> add;
+    std::vector<std::pair<TuneKey, TuneVal>> add;
     for (const char *p = text; *p;) {
         const char *nl = p;
         while (*nl && *nl != '\n') nl++;
         TuneKey key;
-        int rows;
-        if (!parse_line(p, nl, &key, &rows)) return DWT2_E_ARG;
-        add.emplace_back(key, rows);
+        TuneVal val;
+        if (!parse_line(p, nl, &key, &val)) return DWT2_E_ARG;
+        add.emplace_back(key, val);
         p = *nl ? nl + 1 : nl;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -141,11 +141,15 @@ constexpr int kFusedRows[3][kFusedRowsMax] = {{2, 3, 0}, {2, 3, 4}, {3, 6, 0}};
 constexpr int kFusedRowsFp64[3] = {3, 4, 6};
 bool fused_rows_supported(int wavelet, bool fp64, int rows);
 // buffers: 2 = double-buffered LDS planes (one barrier per spatial step), 1 =
-// single-buffered (two per step; FP32 only).
-hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, int buffers, const FwdArgs &a,
-                                hipStream_t s);
-hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, int buffers, const InvArgs &a,
-                                hipStream_t s);
+// single-buffered (two per step; FP32 only).  order: the order in which the
+// XCDs take the tiles, kOrderRuns (each XCD a contiguous row-major run) or
+// kOrderBands (each XCD a band of tile columns, all on the same rows at a
+// time); it changes speed only.
+constexpr int kOrderRuns = 1, kOrderBands = 2;
+hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, int buffers, int order,
+                                const FwdArgs &a, hipStream_t s);
+hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, int buffers, int order,
+                                const InvArgs &a, hipStream_t s);
 // Tiles of the fused kernel for one W x H level at `rows` (0 when a side is
 // below 2 or the height is not built).
 long long fused_tile_count(int wavelet, int rows, int W, int H);

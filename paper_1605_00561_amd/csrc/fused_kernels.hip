@@ -34,8 +34,12 @@
 // output height of every built tile height, so every output sees the same c
 // and the same arithmetic whatever the tile height, and the coefficients are
 // bitwise independent of it.
-// Tiles are numbered so that each XCD (work-group id mod 8) takes a
-// contiguous row-major run, so neighbouring tiles share their halo in L2.
+// Tile order: work-group id mod 8 is the XCD.  In the run order each XCD
+// takes a contiguous row-major run of tiles; in the band order each XCD sweeps
+// one eighth of the tile columns from the top down, so that all XCDs work on
+// the same rows at a time.  Either way neighbouring tiles share their halo in
+// one L2.  The host picks the order per level (measured: runs up to about
+// 2^27 pixels, bands above); it does not change the result.
 #include <string.h>
 
 #include "dwt2_internal.h"
@@ -136,6 +140,17 @@ __device__ __forceinline__ int xcd_tile(int ntiles)
     const int per = gridDim.x >> 3;  // grid is a multiple of 8
     const int t = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     return t < ntiles ? t : -1;
+}
+
+// Band order over ntx x (ntiles / ntx) tiles: XCD x sweeps the tile columns
+// [x R, x R + R), R = ceil(ntx / 8), row by row; the grid is 8 R nty, and the
+// work-groups past a band's tiles get -1.
+__device__ __forceinline__ int band_tile(int ntx, int ntiles)
+{
+    const int R = (ntx + 7) / 8, x = blockIdx.x & 7, k = blockIdx.x >> 3;
+    const int bw = min(R, ntx - x * R), nty = ntiles / ntx;
+    if (bw <= 0 || k / bw >= nty) return -1;
+    return (k / bw) * ntx + x * R + k % bw;
 }
 
 // Row planes in LDS: [buffer][component][tile row + PAD][lane]; the PAD rows
@@ -515,11 +530,11 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int t
 }
 
 template <int WAV, int RB, typename T, int NB>
-__global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, int ntiles)
+__global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, int ntiles, int bands)
 {
     constexpr int HQ = Halo<WAV>::HQ;
     __shared__ T sm[Geo<WAV, RB>::template plane_elems<NB>()];
-    const int tile = xcd_tile(ntiles);
+    const int tile = bands ? band_tile(ntx, ntiles) : xcd_tile(ntiles);
     if (tile < 0) return;  // uniform over the work-group
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
     const int tc = tile % ntx, tr = tile / ntx;
@@ -533,11 +548,11 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_forward(FwdArgs a, int ntx, 
 }
 
 template <int WAV, int RB, typename T, int NB>
-__global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, int ntiles)
+__global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, int ntiles, int bands)
 {
     constexpr int HQ = Halo<WAV>::HQ;
     __shared__ T sm[Geo<WAV, RB>::template plane_elems<NB>()];
-    const int tile = xcd_tile(ntiles);
+    const int tile = bands ? band_tile(ntx, ntiles) : xcd_tile(ntiles);
     if (tile < 0) return;
     const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
     const int tc = tile % ntx, tr = tile / ntx;
@@ -685,7 +700,7 @@ __global__ __launch_bounds__(256) void k_upload(uint32_t *dst, int n, UploadChun
 }
 
 struct Grid {
-    int ntx, ntiles, blocks;
+    int ntx, ntiles, blocks, bands;
 };
 
 long long tile_count(int HQ, int TY, long long W, long long H)
@@ -697,45 +712,46 @@ long long tile_count(int HQ, int TY, long long W, long long H)
 }
 
 template <int WAV, int RB>
-Grid fused_grid(int W, int H)
+Grid fused_grid(int W, int H, int order)
 {
     using G = Geo<WAV, RB>;
     Grid g;
     g.ntx = ((W + 1) / 2 + G::IX - 1) / G::IX;
-    g.ntiles = (int)tile_count(G::HQ, G::TY, W, H);
-    g.blocks = (g.ntiles + 7) / 8 * 8;
+    g.ntiles = (int)tile_count(G::HQ, G::TY, W, H);  // ntx x nty
+    g.bands = order == kOrderBands;
+    g.blocks = g.bands ? 8 * ((g.ntx + 7) / 8) * (g.ntiles / g.ntx) : (g.ntiles + 7) / 8 * 8;
     return g;
 }
 
 // FP64 kernels are built at one height per wavelet and double-buffered;
 // FP32 kernels at every height, single- and double-buffered.
 template <int WAV, int RB>
-hipError_t fused_fwd(bool fp64, bool single, const FwdArgs &a, hipStream_t s)
+hipError_t fused_fwd(bool fp64, bool single, int order, const FwdArgs &a, hipStream_t s)
 {
-    const Grid g = fused_grid<WAV, RB>(a.W, a.H);
+    const Grid g = fused_grid<WAV, RB>(a.W, a.H, order);
     const dim3 grid(g.blocks), block(NTHREADS);
     if constexpr (RB == kFusedRowsFp64[WAV])
-        if (fp64 && !single) return launch(k_fused_forward<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles);
+        if (fp64 && !single) return launch(k_fused_forward<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
     if (fp64) return hipErrorInvalidValue;
-    return single ? launch(k_fused_forward<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles)
-                  : launch(k_fused_forward<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles);
+    return single ? launch(k_fused_forward<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
+                  : launch(k_fused_forward<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
 }
 
 template <int WAV, int RB>
-hipError_t fused_inv(bool fp64, bool single, const InvArgs &a, hipStream_t s)
+hipError_t fused_inv(bool fp64, bool single, int order, const InvArgs &a, hipStream_t s)
 {
-    const Grid g = fused_grid<WAV, RB>(a.W, a.H);
+    const Grid g = fused_grid<WAV, RB>(a.W, a.H, order);
     const dim3 grid(g.blocks), block(NTHREADS);
     if constexpr (RB == kFusedRowsFp64[WAV])
-        if (fp64 && !single) return launch(k_fused_inverse<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles);
+        if (fp64 && !single) return launch(k_fused_inverse<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
     if (fp64) return hipErrorInvalidValue;
-    return single ? launch(k_fused_inverse<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles)
-                  : launch(k_fused_inverse<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles);
+    return single ? launch(k_fused_inverse<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
+                  : launch(k_fused_inverse<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
 }
 
 // The launcher of (wavelet, rows), over the built heights.
 template <bool INV, int WAV, int I = 0>
-hipError_t dispatch_rows(int rows, bool fp64, bool single, const void *args, hipStream_t s)
+hipError_t dispatch_rows(int rows, bool fp64, bool single, int order, const void *args, hipStream_t s)
 {
     if constexpr (I == kFusedRowsMax) {
         return hipErrorInvalidValue;
@@ -743,24 +759,25 @@ hipError_t dispatch_rows(int rows, bool fp64, bool single, const void *args, hip
         constexpr int RB = kFusedRows[WAV][I];
         if constexpr (RB > 0) {
             if (rows == RB)
-                return INV ? fused_inv<WAV, RB>(fp64, single, *(const InvArgs *)args, s)
-                           : fused_fwd<WAV, RB>(fp64, single, *(const FwdArgs *)args, s);
+                return INV ? fused_inv<WAV, RB>(fp64, single, order, *(const InvArgs *)args, s)
+                           : fused_fwd<WAV, RB>(fp64, single, order, *(const FwdArgs *)args, s);
         }
-        return dispatch_rows<INV, WAV, I + 1>(rows, fp64, single, args, s);
+        return dispatch_rows<INV, WAV, I + 1>(rows, fp64, single, order, args, s);
     }
 }
 
 template <bool INV>
-hipError_t dispatch(int wavelet, bool fp64, int rows, int buffers, const void *args, hipStream_t s)
+hipError_t dispatch(int wavelet, bool fp64, int rows, int buffers, int order, const void *args,
+                    hipStream_t s)
 {
     if (!fused_rows_supported(wavelet, fp64, rows) || (buffers != 1 && buffers != 2) ||
-        (fp64 && buffers != 2))
+        (fp64 && buffers != 2) || (order != kOrderRuns && order != kOrderBands))
         return hipErrorInvalidValue;
     const bool single = buffers == 1;
     switch (wavelet) {
-    case CDF53: return dispatch_rows<INV, CDF53>(rows, fp64, single, args, s);
-    case CDF97: return dispatch_rows<INV, CDF97>(rows, fp64, single, args, s);
-    case DD137: return dispatch_rows<INV, DD137>(rows, fp64, single, args, s);
+    case CDF53: return dispatch_rows<INV, CDF53>(rows, fp64, single, order, args, s);
+    case CDF97: return dispatch_rows<INV, CDF97>(rows, fp64, single, order, args, s);
+    case DD137: return dispatch_rows<INV, DD137>(rows, fp64, single, order, args, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -793,16 +810,16 @@ bool fused_rows_supported(int wavelet, bool fp64, int rows)
     return false;
 }
 
-hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, int buffers, const FwdArgs &a,
-                                hipStream_t s)
+hipError_t launch_fused_forward(int wavelet, bool fp64, int rows, int buffers, int order,
+                                const FwdArgs &a, hipStream_t s)
 {
-    return dispatch<false>(wavelet, fp64, rows, buffers, &a, s);
+    return dispatch<false>(wavelet, fp64, rows, buffers, order, &a, s);
 }
 
-hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, int buffers, const InvArgs &a,
-                                hipStream_t s)
+hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, int buffers, int order,
+                                const InvArgs &a, hipStream_t s)
 {
-    return dispatch<true>(wavelet, fp64, rows, buffers, &a, s);
+    return dispatch<true>(wavelet, fp64, rows, buffers, order, &a, s);
 }
 
 long long fused_tile_count(int wavelet, int rows, int W, int H)

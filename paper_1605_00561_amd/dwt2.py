@@ -39,11 +39,16 @@ EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_
            "dwt2_last_hip_error", "dwt2_version", "dwt2_batch_workspace_bytes",
            "dwt2_forward_batch", "dwt2_inverse_batch", "dwt2_server_create", "dwt2_server_submit",
            "dwt2_server_wait", "dwt2_server_replay", "dwt2_server_destroy", "dwt2_autotune",
-           "dwt2_tile_rows", "dwt2_tune_export", "dwt2_tune_import", "dwt2_tune_reset"]
+           "dwt2_tile_rows", "dwt2_tile_order", "dwt2_tune_export", "dwt2_tune_import",
+           "dwt2_tune_reset"]
 BATCH_MAX = 65536
 # Tile heights the fused kernel is built for (FP32 lifting; FP64: one each).
 TILE_ROWS = {"cdf53": (2, 3), "cdf97": (2, 3, 4), "dd137": (3, 6)}
 TILE_ROWS_FP64 = {"cdf53": 3, "cdf97": 4, "dd137": 6}
+# Tile orders of the fused kernel (how the XCDs share a level's tiles).
+ORDER_AUTO, ORDER_RUNS, ORDER_BANDS = 0, 1, 2
+ORDERS = {"auto": ORDER_AUTO, "runs": ORDER_RUNS, "bands": ORDER_BANDS,
+          ORDER_AUTO: ORDER_AUTO, ORDER_RUNS: ORDER_RUNS, ORDER_BANDS: ORDER_BANDS}
 
 
 ARITH_AUTO, ARITH_FP32, ARITH_FP64 = 0, 1, 2
@@ -54,7 +59,7 @@ ARITHS = {"auto": ARITH_AUTO, "fp32": ARITH_FP32, "fp64": ARITH_FP64,
 class Options(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_int), ("scheme", ctypes.c_int), ("arithmetic", ctypes.c_int),
                 ("tile_rows", ctypes.c_int), ("lds_buffers", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("tile_order", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class Image(ctypes.Structure):
@@ -136,10 +141,11 @@ def _load() -> ctypes.CDLL:
     L.dwt2_autotune.argtypes = [i, i, i, i, i, vp, pd, vp, pd, i, ctypes.POINTER(Options), vp, sz,
                                 i, vp]
     L.dwt2_tile_rows.argtypes = [i, i, i, i, ctypes.POINTER(Options), ctypes.POINTER(i)]
+    L.dwt2_tile_order.argtypes = [i, i, i, i, ctypes.POINTER(Options), ctypes.POINTER(i)]
     L.dwt2_tune_export.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(sz)]
     L.dwt2_tune_import.argtypes = [ctypes.c_char_p]
     L.dwt2_tune_reset.argtypes = []
-    for f in ("autotune", "tile_rows", "tune_export", "tune_import", "tune_reset"):
+    for f in ("autotune", "tile_rows", "tile_order", "tune_export", "tune_import", "tune_reset"):
         getattr(L, "dwt2_" + f).restype = i
     return L
 
@@ -152,13 +158,14 @@ def library() -> ctypes.CDLL:
 
 
 def make_options(norm="unit_dc", scheme="auto", arithmetic="auto", tile_rows=0,
-                 lds_buffers=0) -> Options:
+                 lds_buffers=0, tile_order="auto") -> Options:
     o = Options()
     o.norm = NORMS[norm]
     o.scheme = SCHEMES[scheme]
     o.arithmetic = ARITHS[arithmetic]
     o.tile_rows = int(tile_rows)
     o.lds_buffers = int(lds_buffers)
+    o.tile_order = ORDERS[tile_order] if tile_order in ORDERS else int(tile_order)
     return o
 
 
@@ -210,6 +217,14 @@ def dwt2_tile_rows(inverse, wavelet, width, height, opt: Options | None = None):
     r = ctypes.c_int(0)
     st = _lib.dwt2_tile_rows(int(bool(inverse)), WAVELETS[wavelet], width, height,
                              ctypes.byref(opt) if opt is not None else None, ctypes.byref(r))
+    return st, r.value
+
+
+def dwt2_tile_order(inverse, wavelet, width, height, opt: Options | None = None):
+    """(status, order)."""
+    r = ctypes.c_int(0)
+    st = _lib.dwt2_tile_order(int(bool(inverse)), WAVELETS[wavelet], width, height,
+                              ctypes.byref(opt) if opt is not None else None, ctypes.byref(r))
     return st, r.value
 
 
@@ -328,7 +343,7 @@ def _stream_handle(stream):
 
 
 def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, arithmetic,
-               tile_rows, lds_buffers=0):
+               tile_rows, lds_buffers=0, tile_order="auto"):
     """Allocate out / workspace as needed and run call(opt, ws, ws_bytes) -> status,
     a closure over the C entry point with the tensors' pointers."""
     import torch
@@ -337,7 +352,7 @@ def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, ari
     if out is None:
         out = torch.empty((h, w), dtype=torch.float32, device=x.device)
     _check_image(out)
-    opt = make_options(norm, scheme, arithmetic, tile_rows, lds_buffers)
+    opt = make_options(norm, scheme, arithmetic, tile_rows, lds_buffers, tile_order)
     ws, nws = _workspace(wavelet, levels, w, h, opt, x.device, workspace)
     st = call(out, opt, ws.data_ptr() if ws is not None else None, nws)
     if st != OK:
@@ -346,32 +361,35 @@ def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, ari
 
 
 def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
-            workspace=None, stream=None, arithmetic="auto", tile_rows=0, lds_buffers=0):
+            workspace=None, stream=None, arithmetic="auto", tile_rows=0, lds_buffers=0,
+            tile_order="auto"):
     """Forward DWT of a (H, W) float32 device tensor; returns the Mallat layout."""
     def call(y, opt, ws, nws):
         return dwt2_forward(wavelet, levels, img.shape[1], img.shape[0], img.data_ptr(),
                             img.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                             nws, _stream_handle(stream))
     return _transform("dwt2_forward", call, img, wavelet, levels, norm, scheme, out, workspace,
-                      arithmetic, tile_rows, lds_buffers)
+                      arithmetic, tile_rows, lds_buffers, tile_order)
 
 
 def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
-            workspace=None, stream=None, arithmetic="auto", tile_rows=0, lds_buffers=0):
+            workspace=None, stream=None, arithmetic="auto", tile_rows=0, lds_buffers=0,
+            tile_order="auto"):
     """Inverse DWT of a (H, W) Mallat-layout float32 device tensor; returns the image."""
     def call(y, opt, ws, nws):
         return dwt2_inverse(wavelet, levels, coef.shape[1], coef.shape[0], coef.data_ptr(),
                             coef.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                             nws, _stream_handle(stream))
     return _transform("dwt2_inverse", call, coef, wavelet, levels, norm, scheme, out, workspace,
-                      arithmetic, tile_rows, lds_buffers)
+                      arithmetic, tile_rows, lds_buffers, tile_order)
 
 
 def autotune(x, wavelet="cdf53", levels=1, inverse=False, norm="unit_dc", repeats=20, out=None,
              workspace=None, stream=None):
     """dwt2_autotune: the forward (or inverse) transform of x, as forward() (or
-    inverse()) computes it, timing every built tile height at every level and
-    recording the fastest in the process-wide table.  Blocks until done."""
+    inverse()) computes it, timing every built tile height in both tile orders
+    at every level and recording the fastest in the process-wide table.
+    Blocks until done."""
     def call(y, opt, ws, nws):
         return dwt2_autotune(inverse, wavelet, levels, x.shape[1], x.shape[0], x.data_ptr(),
                              x.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
@@ -390,6 +408,17 @@ def tile_rows(wavelet, width, height, inverse=False, norm="unit_dc", arithmetic=
     return r
 
 
+def tile_order(wavelet, width, height, inverse=False, norm="unit_dc", arithmetic="auto",
+               order="auto") -> str:
+    """Tile order ("runs" or "bands") a call with these options uses for one
+    width x height level."""
+    st, r = dwt2_tile_order(inverse, wavelet, width, height,
+                            make_options(norm, "auto", arithmetic, tile_order=order))
+    if st != OK:
+        raise Dwt2Error(st, "dwt2_tile_order")
+    return {ORDER_RUNS: "runs", ORDER_BANDS: "bands"}[r]
+
+
 def save_tuning(path, arch=None):
     """Write the tuned table to a JSON file, tagged with the GPU architecture
     (that of device 0 unless given)."""
@@ -400,7 +429,8 @@ def save_tuning(path, arch=None):
     if arch is None:
         import torch
         arch = torch.cuda.get_device_properties(0).gcnArchName
-    entries = [dict(zip(("wavelet", "inverse", "width", "height", "rows"), map(int, l.split())))
+    entries = [dict(zip(("wavelet", "inverse", "width", "height", "rows", "order"),
+                        map(int, l.split())))
                for l in text.splitlines()]
     with open(path, "w") as f:
         json.dump({"arch": arch, "entries": entries}, f, indent=1)
@@ -417,8 +447,8 @@ def load_tuning(path, arch=None) -> int:
         arch = torch.cuda.get_device_properties(0).gcnArchName
     if d.get("arch") != arch:
         raise ValueError(f"tuning for {d.get('arch')!r}, this device is {arch!r}")
-    text = "".join(f"{e['wavelet']} {e['inverse']} {e['width']} {e['height']} {e['rows']}\n"
-                   for e in d["entries"])
+    text = "".join(f"{e['wavelet']} {e['inverse']} {e['width']} {e['height']} {e['rows']}"
+                   f" {e.get('order', 0)}\n" for e in d["entries"])
     st = dwt2_tune_import(text)
     if st != OK:
         raise Dwt2Error(st, "dwt2_tune_import")

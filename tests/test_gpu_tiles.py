@@ -1,12 +1,12 @@
-"""GPU tests of the fused kernel's tile heights and of dwt2_autotune (through
-the C ABI).
+"""GPU tests of the fused kernel's tile heights, tile orders and of
+dwt2_autotune (through the C ABI).
 
-Every built height must give bitwise the coefficients (and samples) of the
-automatic choice, in both directions, for all wavelets, at sizes that span
-several centring cells and end in ragged tiles; the automatic choice is held
-to the oracle by the parity tests, and again here on the same inputs.
-dwt2_autotune must leave in dst exactly what the plain call gives and record
-only built heights.
+Every built height and both tile orders must give bitwise the coefficients
+(and samples) of the automatic choice, in both directions, for all wavelets,
+at sizes that span several centring cells and end in ragged tiles; the
+automatic choice is held to the oracle by the parity tests, and again here
+on the same inputs.  dwt2_autotune must leave in dst exactly what the plain
+call gives and record only built heights and valid orders.
 """
 import numpy as np
 import pytest
@@ -46,13 +46,20 @@ def test_every_height_gives_the_same_bits(wav, norm):
         what = f"{wav} {norm} {w}x{h} L{lev}"
         for rows in dwt2.TILE_ROWS[wav]:
             for nb in (1, 2):  # single- and double-buffered LDS planes
-                y = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows,
-                                 lds_buffers=nb)
-                z = dwt2.inverse(base, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows,
-                                 lds_buffers=nb)
-                torch.cuda.synchronize()
-                assert torch.equal(y, base), f"forward {what} rows {rows} buffers {nb}"
-                assert torch.equal(z, back), f"inverse {what} rows {rows} buffers {nb}"
+                for order in ("runs", "bands"):
+                    y = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), tile_rows=rows,
+                                     lds_buffers=nb, tile_order=order)
+                    z = dwt2.inverse(base, wav, lev, norm, out=empty_dev(h, w, pitch),
+                                     tile_rows=rows, lds_buffers=nb, tile_order=order)
+                    torch.cuda.synchronize()
+                    assert torch.equal(y, base), f"forward {what} rows {rows} buffers {nb} {order}"
+                    assert torch.equal(z, back), f"inverse {what} rows {rows} buffers {nb} {order}"
+        for order in ("runs", "bands"):  # FP64 lifting, both orders
+            y = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), arithmetic="fp64",
+                             tile_order=order)
+            y0 = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), arithmetic="fp64")
+            torch.cuda.synchronize()
+            assert torch.equal(y, y0), f"fp64 forward {what} {order}"
         if norm == "unit_dc":
             got = to_host(base)
             check(got, oracle.forward(x.astype(np.float64), wav, lev, norm),
@@ -62,14 +69,47 @@ def test_every_height_gives_the_same_bits(wav, norm):
 
 
 def test_every_height_at_8192():
-    """The headline level (8192^2, 9/7) at every height: identical bits."""
+    """The headline level (8192^2, 9/7) at every height and in both tile
+    orders: identical bits."""
     x = to_dev(wl.workload_image("cdf97_8192_l1"))
     base = dwt2.forward(x, "cdf97", 1)
     back = dwt2.inverse(base, "cdf97", 1)
     for rows in dwt2.TILE_ROWS["cdf97"]:
         for nb in (1, 2):
-            assert torch.equal(dwt2.forward(x, "cdf97", 1, tile_rows=rows, lds_buffers=nb), base)
-            assert torch.equal(dwt2.inverse(base, "cdf97", 1, tile_rows=rows, lds_buffers=nb), back)
+            for order in ("runs", "bands"):
+                assert torch.equal(dwt2.forward(x, "cdf97", 1, tile_rows=rows, lds_buffers=nb,
+                                                tile_order=order), base)
+                assert torch.equal(dwt2.inverse(base, "cdf97", 1, tile_rows=rows, lds_buffers=nb,
+                                                tile_order=order), back)
+
+
+@pytest.mark.parametrize("wav", ["cdf53", "cdf97"])
+def test_both_orders_at_16384(wav):
+    """16384^2, where the rule picks the band order: the run order gives the
+    same bits in both directions."""
+    x = to_dev(wl.workload_image(f"{wav}_16384_l5"))
+    assert dwt2.tile_order(wav, 16384, 16384) == "bands"
+    base = dwt2.forward(x, wav, 1)
+    assert torch.equal(dwt2.forward(x, wav, 1, tile_order="runs"), base)
+    back = dwt2.inverse(base, wav, 1)
+    assert torch.equal(dwt2.inverse(base, wav, 1, tile_order="runs"), back)
+    del base, back
+    torch.cuda.empty_cache()
+
+
+def test_band_order_with_fewer_tile_columns_than_xcds():
+    """Levels 1 to 7 tile columns wide leave some XCDs without a band; every
+    tile is still computed once (bits equal to the run order, NaN-filled
+    outputs would show a skipped tile)."""
+    rng = np.random.default_rng(402)
+    for w in (2, 60, 130, 250, 500, 800, 1000):
+        for wav in WAVELETS:
+            x = to_dev(rng.integers(0, 256, size=(97, w)).astype(np.float32))
+            a = dwt2.forward(x, wav, 1, tile_order="runs", out=empty_dev(97, w))
+            b = dwt2.forward(x, wav, 1, tile_order="bands", out=empty_dev(97, w))
+            torch.cuda.synchronize()
+            assert torch.equal(a, b), (w, wav)
+            assert bool(torch.isfinite(b).all()), (w, wav)
 
 
 @pytest.mark.parametrize("wav", WAVELETS)
@@ -94,9 +134,11 @@ def test_autotune_leaves_the_plain_result_and_records_built_heights(wav):
         cw, ch = (cw + 1) // 2, (ch + 1) // 2
     wid = dwt2.WAVELETS[wav]
     assert sorted(e[:4] for e in entries) == sorted((wid, d, a, b) for d in (0, 1) for (a, b) in sizes)
-    for (_, d, a, b, rows) in entries:
+    for (_, d, a, b, rows, order) in entries:
         assert rows in dwt2.TILE_ROWS[wav]
+        assert order in (dwt2.ORDER_RUNS, dwt2.ORDER_BANDS)
         assert dwt2.tile_rows(wav, a, b, inverse=bool(d)) == rows
+        assert dwt2.tile_order(wav, a, b, inverse=bool(d)) == ("runs", "bands")[order - 1]
     # calls now run at the tuned heights and still give the same bits
     assert torch.equal(dwt2.forward(x, wav, lev), want)
     assert torch.equal(dwt2.inverse(want, wav, lev), want_inv)

@@ -57,7 +57,7 @@ def test_lds_buffering_option_is_validated():
         assert _fwd(dwt2.make_options(scheme=scheme, lds_buffers=1)) == dwt2.E_UNSUPPORTED
         assert _fwd(dwt2.make_options(scheme=scheme, lds_buffers=2)) == dwt2.E_UNSUPPORTED
     o = dwt2.make_options(lds_buffers=1)
-    o.reserved[2] = 1
+    o.reserved[1] = 1
     assert _fwd(o) == dwt2.E_ARG
 
 
@@ -130,11 +130,12 @@ def test_export_import_round_trip():
     assert dwt2.dwt2_tune_import(text) == dwt2.OK
     st, out = dwt2.dwt2_tune_export()
     assert st == dwt2.OK
-    assert out == "0 0 40 30 3\n1 0 100 60 2\n1 1 100 60 3\n2 0 5000 7 6\n"  # key order
+    # key order; entries imported without a tile order export order 0
+    assert out == "0 0 40 30 3 0\n1 0 100 60 2 0\n1 1 100 60 3 0\n2 0 5000 7 6 0\n"
     # replacing an entry keeps one line per key
-    assert dwt2.dwt2_tune_import("1 0 100 60 4") == dwt2.OK  # no final newline needed
+    assert dwt2.dwt2_tune_import("1 0 100 60 4 2") == dwt2.OK  # no final newline needed
     st, out2 = dwt2.dwt2_tune_export()
-    assert out2 == out.replace("1 0 100 60 2", "1 0 100 60 4")
+    assert out2 == out.replace("1 0 100 60 2 0", "1 0 100 60 4 2")
     assert dwt2.dwt2_tune_reset() == dwt2.OK
     assert dwt2.dwt2_tune_import(out2) == dwt2.OK
     assert dwt2.dwt2_tune_export() == (dwt2.OK, out2)
@@ -146,13 +147,13 @@ def test_export_buffer_too_small():
     n = ctypes.c_size_t()
     lib = dwt2.library()
     assert lib.dwt2_tune_export(None, 0, ctypes.byref(n)) == dwt2.E_SIZE
-    assert n.value == len("1 0 8192 8192 4\n")
+    assert n.value == len("1 0 8192 8192 4 0\n")
     buf = ctypes.create_string_buffer(b"x" * 8, n.value)
     assert lib.dwt2_tune_export(buf, n.value, ctypes.byref(n)) == dwt2.E_SIZE  # no room for NUL
     assert buf.raw[0] == 0
     buf = ctypes.create_string_buffer(n.value + 1)
     assert lib.dwt2_tune_export(buf, n.value + 1, ctypes.byref(n)) == dwt2.OK
-    assert buf.value == b"1 0 8192 8192 4\n"
+    assert buf.value == b"1 0 8192 8192 4 0\n"
     assert lib.dwt2_tune_export(None, 4, ctypes.byref(n)) == dwt2.E_ARG
     assert lib.dwt2_tune_export(buf, 4, None) == dwt2.E_ARG
 
@@ -162,7 +163,8 @@ def test_export_buffer_too_small():
     "1 0 8192 8192 4 \n", "1 0 8192 8192 5\n", "3 0 64 64 2\n", "1 2 64 64 2\n",
     "1 0 1 64 2\n", "1 0 64 1 2\n", "1 0 -64 64 2\n", "1 0 64 64 +2\n", "1 0 64 64 2\r\n",
     "1 0 99999999999 64 2\n", "x\n", "\n", "0 0 64 64 4\n", "2 0 64 64 4\n", "1 0 64 64 7\n",
-    "1 0 64 64 2\n\n"])
+    "1 0 64 64 2\n\n", "1 0 64 64 2 3\n", "1 0 64 64 2 1 1\n", "1 0 64 64 2 -1\n",
+    "1 0 64 64 2 1 \n"])
 def test_import_rejects_malformed_text_atomically(bad):
     assert dwt2.dwt2_tune_import("1 1 64 64 3\n") == dwt2.OK
     before = dwt2.dwt2_tune_export()
@@ -227,8 +229,8 @@ def test_tuning_file_round_trip_and_architecture_check(tmp_path):
     dwt2.save_tuning(path, arch="gfx950")
     d = json.load(open(path))
     assert d["arch"] == "gfx950"
-    assert {(e["wavelet"], e["inverse"], e["width"], e["height"], e["rows"]) for e in d["entries"]} == \
-        {(1, 0, 8192, 8192, 3), (2, 1, 300, 200, 6)}
+    assert {(e["wavelet"], e["inverse"], e["width"], e["height"], e["rows"], e["order"])
+            for e in d["entries"]} == {(1, 0, 8192, 8192, 3, 0), (2, 1, 300, 200, 6, 0)}
     assert dwt2.dwt2_tune_reset() == dwt2.OK
     assert dwt2.load_tuning(path, arch="gfx950") == 2
     assert dwt2.tile_rows("cdf97", 8192, 8192) == 3
@@ -240,3 +242,85 @@ def test_tuning_file_round_trip_and_architecture_check(tmp_path):
     with pytest.raises(dwt2.Dwt2Error):  # a height that is not built: the table stays as it was
         dwt2.load_tuning(path, arch="gfx950")
     assert dwt2.tile_rows("cdf97", 64, 64) == dwt2.tile_rows("cdf97", 64, 64, rows=2)
+
+
+# --- tile order -----------------------------------------------------------------
+
+def test_tile_order_option_validation():
+    """dst == src makes every call an error after option parsing (DWT2_E_ALIAS
+    means the options were accepted); nothing is launched."""
+    for order in ("runs", "bands"):
+        assert _fwd(dwt2.make_options(tile_order=order), dst=FAKE) == dwt2.E_ALIAS
+        for scheme in ("sweldens", "rowcol", "polyphase*"):
+            assert _fwd(dwt2.make_options(scheme=scheme, tile_order=order), dst=FAKE) == \
+                dwt2.E_UNSUPPORTED
+        assert _fwd(dwt2.make_options(arithmetic="fp64", tile_order=order), dst=FAKE) == dwt2.E_ALIAS
+    for bad in (3, -1, 7):
+        assert _fwd(dwt2.make_options(tile_order=bad), dst=FAKE) == dwt2.E_UNSUPPORTED
+
+
+def test_tile_order_rule():
+    """Bands from 2^27 pixels on when the level is at least 2048 pixels wide."""
+    for wav in ("cdf53", "cdf97", "dd137"):
+        for inverse in (False, True):
+            assert dwt2.tile_order(wav, 8192, 8192, inverse=inverse) == "runs"
+            assert dwt2.tile_order(wav, 10240, 10240, inverse=inverse) == "runs"
+            assert dwt2.tile_order(wav, 16384, 8192, inverse=inverse) == "bands"   # exactly 2^27
+            assert dwt2.tile_order(wav, 16384, 8191, inverse=inverse) == "runs"
+            assert dwt2.tile_order(wav, 16384, 16384, inverse=inverse) == "bands"
+            assert dwt2.tile_order(wav, 2048, 65536, inverse=inverse) == "bands"
+            assert dwt2.tile_order(wav, 2047, 65600, inverse=inverse) == "runs"   # too narrow
+            assert dwt2.tile_order(wav, 16384, 16384, arithmetic="fp64") == "bands"
+    assert dwt2.tile_order("cdf97", 16384, 16384, order="runs") == "runs"      # explicit wins
+    assert dwt2.tile_order("cdf97", 64, 64, order="bands") == "bands"
+    st, _ = dwt2.dwt2_tile_order(0, "cdf97", 64, 64, dwt2.make_options(scheme="rowcol"))
+    assert st == dwt2.E_UNSUPPORTED
+    st, _ = dwt2.dwt2_tile_order(0, "cdf97", 1, 64)
+    assert st == dwt2.E_SIZE
+    assert dwt2.library().dwt2_tile_order(0, 1, 64, 64, None, None) == dwt2.E_ARG
+
+
+def test_tuned_order_overrides_the_rule_for_its_key_only():
+    assert dwt2.dwt2_tune_import("1 0 8192 8192 4 2\n1 1 16384 16384 3 1\n0 0 16384 16384 3\n") \
+        == dwt2.OK
+    assert dwt2.tile_order("cdf97", 8192, 8192) == "bands"
+    assert dwt2.tile_rows("cdf97", 8192, 8192) == 4
+    assert dwt2.tile_order("cdf97", 8192, 8192, inverse=True) == "runs"          # rule
+    assert dwt2.tile_order("cdf97", 16384, 16384, inverse=True) == "runs"
+    assert dwt2.tile_order("cdf53", 16384, 16384) == "bands"                     # order 0: rule
+    assert dwt2.tile_rows("cdf53", 16384, 16384) == 3
+    assert dwt2.tile_order("cdf97", 8192, 8192, order="runs") == "runs"          # explicit wins
+    assert dwt2.tile_order("cdf97", 8192, 8192, arithmetic="fp64") == "runs"     # FP32 entries only
+    assert dwt2.dwt2_tune_reset() == dwt2.OK
+    assert dwt2.tile_order("cdf97", 8192, 8192) == "runs"
+
+
+def test_autotune_and_batches_reject_an_explicit_order():
+    lib = dwt2.library()
+    for order in (1, 2):
+        o = dwt2.make_options(tile_order=order)
+        assert lib.dwt2_autotune(0, 1, 1, 16, 16, FAKE, 16, FAKE + (1 << 24), 16, 0,
+                                 ctypes.byref(o), None, 0, 5, None) == dwt2.E_UNSUPPORTED
+        arr = (dwt2.Image * 1)(dwt2.Image(1, 1, 64, 64, FAKE, 64, FAKE + (1 << 24), 64))
+        st, _ = dwt2.dwt2_batch_workspace_bytes(arr, 1, o)
+        assert st == dwt2.E_UNSUPPORTED
+
+
+def test_tuning_file_keeps_the_order(tmp_path):
+    import json
+    assert dwt2.dwt2_tune_import("1 0 16384 16384 4 1\n0 1 8192 8192 3 2\n") == dwt2.OK
+    path = str(tmp_path / "tuning.json")
+    dwt2.save_tuning(path, arch="gfx950")
+    assert dwt2.dwt2_tune_reset() == dwt2.OK
+    assert dwt2.load_tuning(path, arch="gfx950") == 2
+    assert dwt2.tile_order("cdf97", 16384, 16384) == "runs"
+    assert dwt2.tile_order("cdf53", 8192, 8192, inverse=True) == "bands"
+    # a file written before orders were recorded still loads (the rule decides)
+    d = json.load(open(path))
+    for e in d["entries"]:
+        del e["order"]
+    json.dump(d, open(path, "w"))
+    assert dwt2.dwt2_tune_reset() == dwt2.OK
+    assert dwt2.load_tuning(path, arch="gfx950") == 2
+    assert dwt2.tile_order("cdf97", 16384, 16384) == "bands"
+    assert dwt2.tile_rows("cdf97", 16384, 16384) == 4
