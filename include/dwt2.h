@@ -376,7 +376,8 @@ int dwt2_server_destroy(dwt2_server *server);
  * dwt2_autotune runs the transform that dwt2_forward (inverse == 0) or
  * dwt2_inverse (inverse != 0) runs with the same arguments and leaves the same
  * result in dst.  Along the way it runs each level `repeats` times at every
- * built FP32 height in both tile orders (two passes), times the runs with HIP
+ * built FP32 height in both tile orders (three passes, each after one untimed
+ * launch of the candidate), times the runs with HIP
  * events on `stream`, and records the fastest height and order for (wavelet,
  * direction, level width, level height) in a table shared by the process
  * (entries are replaced; the table holds at most 4096 entries, further sizes

@@ -626,7 +626,8 @@ DWT2_EXPORT int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext
 namespace {
 
 // Mean time of `repeats` back-to-back launches of one level at `rows` and
-// `order`, in ms.
+// `order`, in ms, after one untimed launch (the previous candidate's
+// traffic and any first-launch cost stay out of the timing).
 int time_level(bool inverse, const Checked &c, const void *args, int rows, int order, int repeats,
                hipEvent_t e0, hipEvent_t e1, hipStream_t stream, float *ms)
 {
@@ -636,7 +637,8 @@ int time_level(bool inverse, const Checked &c, const void *args, int rows, int o
                        : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg), order,
                                                     *(const dwt2::FwdArgs *)args, stream);
     };
-    hipError_t e = hipEventRecord(e0, stream);
+    hipError_t e = run();
+    if (e == hipSuccess) e = hipEventRecord(e0, stream);
     for (int i = 0; i < repeats && e == hipSuccess; i++) e = run();
     if (e == hipSuccess) e = hipEventRecord(e1, stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -663,20 +665,22 @@ int tune(bool inverse, const Checked &c, const float *src, ptrdiff_t src_pitch, 
             fa = forward_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
             args = &fa;
         }
-        // Two passes over every (height, order); each keeps its faster pass.
-        // Every run writes the same level output, so the next level reads the
+        // Three passes over every (height, order), each pass starting at
+        // another candidate; each candidate keeps its fastest pass.  Every
+        // run writes the same level output, so the next level reads the
         // result.
         constexpr int kOrders[2] = {DWT2_ORDER_RUNS, DWT2_ORDER_BANDS};
+        int ncand = 0;
+        while (ncand < dwt2::kFusedRowsMax && cand[ncand] > 0) ncand++;
         float best[dwt2::kFusedRowsMax][2];
-        for (int pass = 0; pass < 2; pass++)
-            for (int i = 0; i < dwt2::kFusedRowsMax && cand[i] > 0; i++)
-                for (int o = 0; o < 2; o++) {
-                    float ms = 0.0f;
-                    const int st =
-                        time_level(inverse, c, args, cand[i], kOrders[o], repeats, e0, e1, stream, &ms);
-                    if (st != DWT2_OK) return st;
-                    best[i][o] = pass == 0 ? ms : std::min(best[i][o], ms);
-                }
+        for (int pass = 0; pass < 3; pass++)
+            for (int j = 0; j < 2 * ncand; j++) {
+                const int q = (j + pass * 2 * ncand / 3) % (2 * ncand), i = q / 2, o = q % 2;
+                float ms = 0.0f;
+                const int st = time_level(inverse, c, args, cand[i], kOrders[o], repeats, e0, e1, stream, &ms);
+                if (st != DWT2_OK) return st;
+                best[i][o] = pass == 0 ? ms : std::min(best[i][o], ms);
+            }
         int pick = 0, pick_o = 0;
         for (int i = 0; i < dwt2::kFusedRowsMax && cand[i] > 0; i++)
             for (int o = 0; o < 2; o++)
