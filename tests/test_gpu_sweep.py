@@ -1,7 +1,7 @@
 """Seeded random sweep of single-image calls against the FP64 oracle.
 
-Each case draws a wavelet, a scheme, the arithmetic, a tile height and LDS
-buffering (fused kernel), the normalisation, a size (biased towards tile
+Each case draws a wavelet, a scheme, the arithmetic, a tile height, LDS
+buffering and tile order (fused kernel), the normalisation, a size (biased towards tile
 boundaries: multiples of the fused tile's output width and height, plus or
 minus one), the level count, row pitches at or above the width, and a base
 offset of one element (so that rows are not 8-byte aligned and the kernels
@@ -49,6 +49,7 @@ def draw_cases(seed=SEED, n=N_CASES):
         scheme = "monolithic*" if fused else str(rng.choice(OTHER_SCHEMES))
         arith = "fp64" if fused and rng.random() < 0.25 else "auto"
         rows, lds = 0, 0
+        order = ("auto", "runs", "bands")[(i // 3) % 3] if fused else "auto"
         if fused and arith != "fp64":
             choices = (0,) + dwt2.TILE_ROWS[wav]       # cycled, so that each is reached
             rows = choices[(i // 3) % len(choices)]
@@ -62,7 +63,8 @@ def draw_cases(seed=SEED, n=N_CASES):
         levels = int(rng.integers(1, min(_levels_possible(w, h), cap) + 1))
         pad = int(rng.choice((0, 0, 1, 3, 64)))
         cases.append(dict(
-            wav=wav, scheme=scheme, arith=arith, rows=rows, lds=lds, w=w, h=h, levels=levels,
+            wav=wav, scheme=scheme, arith=arith, rows=rows, lds=lds, order=order, w=w, h=h,
+            levels=levels,
             norm=norm, src_pitch=w + pad,
             dst_pitch=w + int(rng.choice((0, 1, 64))), offset=int(rng.random() < 0.3),
             real=bool(rng.random() < 0.3), seed=seed * 1000 + i))
@@ -73,7 +75,8 @@ CASES = draw_cases()
 
 
 def case_id(c):
-    return (f"{c['wav']}-{c['scheme']}-{c['arith']}-r{c['rows']}-b{c['lds']}-{c['w']}x{c['h']}"
+    return (f"{c['wav']}-{c['scheme']}-{c['arith']}-r{c['rows']}-b{c['lds']}-{c['order']}"
+            f"-{c['w']}x{c['h']}"
             f"-L{c['levels']}-{c['norm']}-p{c['src_pitch']}.{c['dst_pitch']}-o{c['offset']}"
             f"-{'real' if c['real'] else 'int'}")
 
@@ -81,7 +84,7 @@ def case_id(c):
 def test_draw_covers_every_option():
     """CPU: the sweep reaches every wavelet, scheme, arithmetic, height,
     buffering, pitch and offset kind, and every case is a valid call."""
-    seen = {k: set() for k in ("wav", "scheme", "arith", "lds", "offset", "real", "norm")}
+    seen = {k: set() for k in ("wav", "scheme", "arith", "lds", "order", "offset", "real", "norm")}
     heights = set()
     padded = False
     for c in CASES:
@@ -94,12 +97,14 @@ def test_draw_covers_every_option():
         assert c["src_pitch"] >= c["w"] and c["dst_pitch"] >= c["w"]
         if c["scheme"] != "monolithic*":
             assert c["wav"] != "dd137" and c["arith"] == "auto" and c["rows"] == 0 and c["lds"] == 0
+            assert c["order"] == "auto"
         if c["arith"] == "fp64":
             assert c["rows"] == 0 and c["lds"] == 0
     assert seen["wav"] == {"cdf53", "cdf97", "dd137"}
     assert seen["arith"] == {"auto", "fp64"}
     assert seen["lds"] == {0, 1, 2} and seen["offset"] == {0, 1} and seen["real"] == {False, True}
     assert seen["norm"] == {"unit_dc", "paper"}
+    assert seen["order"] == {"auto", "runs", "bands"}
     assert len(seen["scheme"]) >= 6
     for wav, rows in dwt2.TILE_ROWS.items():
         assert {(wav, r) for r in rows} <= heights, wav
@@ -130,7 +135,7 @@ def test_sweep_case(case):
         return view
 
     kw = dict(norm=c["norm"], scheme=c["scheme"], arithmetic=c["arith"], tile_rows=c["rows"],
-              lds_buffers=c["lds"])
+              lds_buffers=c["lds"], tile_order=c["order"])
     xd = placed(x, c["src_pitch"], c["offset"])
     y = dwt2.forward(xd, c["wav"], c["levels"], out=placed(None, c["dst_pitch"], c["offset"]), **kw)
     torch.cuda.synchronize()
