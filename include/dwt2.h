@@ -176,9 +176,9 @@ typedef DWT2_ENUM(dwt2_arith) { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_A
  * (each with its own L2) share a level's tiles.  RUNS: each XCD takes a
  * contiguous row-major run of tiles.  BANDS: each XCD takes one eighth of the
  * tile columns and sweeps them from the top down, so that all XCDs work on
- * the same rows at a time.  In both, neighbouring tiles meet in one L2 and
- * share their halo there.  Not in the paper (a single-die design); it changes
- * speed only, never the result.  AUTO selects per level: the entry
+ * the same rows at a time.  In both, most neighbouring tiles run on the same
+ * XCD and share their halo in its L2.  Not in the paper; it changes speed
+ * only, never the result.  AUTO selects per level: the entry
  * dwt2_autotune recorded, else BANDS for levels of at least 2^27 pixels and
  * 2048 pixels width, else RUNS.  A nonzero value with another scheme or with
  * the batched calls returns DWT2_E_UNSUPPORTED.
