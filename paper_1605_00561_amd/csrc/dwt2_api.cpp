@@ -76,10 +76,9 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
         (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR ||
          !dwt2::fused_rows_supported(c->wavelet, c->arithmetic == DWT2_ARITH_FP64, c->tile_rows)))
         return DWT2_E_UNSUPPORTED;
-    // Single-buffered planes: fused kernel, FP32 lifting only.
+    // LDS buffering: fused kernel only.
     if (c->lds_buffers != 0 &&
-        (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR || (c->lds_buffers != 1 && c->lds_buffers != 2) ||
-         (c->lds_buffers == 1 && c->arithmetic == DWT2_ARITH_FP64)))
+        (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR || (c->lds_buffers != 1 && c->lds_buffers != 2)))
         return DWT2_E_UNSUPPORTED;
     if (c->tile_order != 0 &&
         (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR ||
@@ -88,7 +87,15 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     return DWT2_OK;
 }
 
-int buffers_of(const Config &c) { return c.lds_buffers == 0 ? 2 : c.lds_buffers; }
+// Default LDS buffering: double for FP32 lifting; single for FP64, whose
+// double-buffered planes (36.9 KB at 9/7) would limit a CU to four
+// work-groups (measured: 8192^2 9/7 forward 130 us single against 138 double,
+// inverse equal).
+int buffers_of(const Config &c)
+{
+    if (c.lds_buffers) return c.lds_buffers;
+    return c.arithmetic == DWT2_ARITH_FP64 ? 1 : 2;
+}
 
 // ---------------------------------------------------------------------------
 // Tile height and tile order of the fused kernel per level.  Tuned entries,

@@ -141,7 +141,7 @@ constexpr int kFusedRows[3][kFusedRowsMax] = {{2, 3, 0}, {2, 3, 4}, {3, 6, 0}};
 constexpr int kFusedRowsFp64[3] = {3, 4, 6};
 bool fused_rows_supported(int wavelet, bool fp64, int rows);
 // buffers: 2 = double-buffered LDS planes (one barrier per spatial step), 1 =
-// single-buffered (two per step; FP32 only).  order: the order in which the
+// single-buffered (two per step).  order: the order in which the
 // XCDs take the tiles, kOrderRuns (each XCD a contiguous row-major run) or
 // kOrderBands (each XCD a band of tile columns, all on the same rows at a
 // time); it changes speed only.

@@ -723,15 +723,17 @@ Grid fused_grid(int W, int H, int order)
     return g;
 }
 
-// FP64 kernels are built at one height per wavelet and double-buffered;
-// FP32 kernels at every height, single- and double-buffered.
+// FP64 kernels are built at one height per wavelet, FP32 kernels at every
+// height; both single- and double-buffered.
 template <int WAV, int RB>
 hipError_t fused_fwd(bool fp64, bool single, int order, const FwdArgs &a, hipStream_t s)
 {
     const Grid g = fused_grid<WAV, RB>(a.W, a.H, order);
     const dim3 grid(g.blocks), block(NTHREADS);
     if constexpr (RB == kFusedRowsFp64[WAV])
-        if (fp64 && !single) return launch(k_fused_forward<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
+        if (fp64)
+            return single ? launch(k_fused_forward<WAV, RB, double, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
+                          : launch(k_fused_forward<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
     if (fp64) return hipErrorInvalidValue;
     return single ? launch(k_fused_forward<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
                   : launch(k_fused_forward<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
@@ -743,7 +745,9 @@ hipError_t fused_inv(bool fp64, bool single, int order, const InvArgs &a, hipStr
     const Grid g = fused_grid<WAV, RB>(a.W, a.H, order);
     const dim3 grid(g.blocks), block(NTHREADS);
     if constexpr (RB == kFusedRowsFp64[WAV])
-        if (fp64 && !single) return launch(k_fused_inverse<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
+        if (fp64)
+            return single ? launch(k_fused_inverse<WAV, RB, double, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
+                          : launch(k_fused_inverse<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
     if (fp64) return hipErrorInvalidValue;
     return single ? launch(k_fused_inverse<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
                   : launch(k_fused_inverse<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
@@ -771,7 +775,7 @@ hipError_t dispatch(int wavelet, bool fp64, int rows, int buffers, int order, co
                     hipStream_t s)
 {
     if (!fused_rows_supported(wavelet, fp64, rows) || (buffers != 1 && buffers != 2) ||
-        (fp64 && buffers != 2) || (order != kOrderRuns && order != kOrderBands))
+        (order != kOrderRuns && order != kOrderBands))
         return hipErrorInvalidValue;
     const bool single = buffers == 1;
     switch (wavelet) {

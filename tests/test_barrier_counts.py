@@ -73,13 +73,13 @@ def test_tile_kernels_have_table1_barriers(counts, direction):
 @pytest.mark.parametrize("direction", ["forward", "inverse"])
 def test_fused_kernels_have_two_barriers_per_pair(counts, direction):
     """Every built tile height, FP32 and FP64, double-buffered: Table 1's count
-    (the height only widens each step).  Single-buffered (FP32): one more
-    barrier per spatial step, except before the first publication."""
+    (the height only widens each step).  Single-buffered: one more barrier
+    per spatial step, except before the first publication."""
     for wid, wav in WAVELET_IDS.items():
         table1 = TABLE1[(wav, "monolithic*")][0]
         built = [(r, "float", 2) for r in dwt2.TILE_ROWS[wav]] + \
                 [(r, "float", 1) for r in dwt2.TILE_ROWS[wav]] + \
-                [(dwt2.TILE_ROWS_FP64[wav], "double", 2)]
+                [(dwt2.TILE_ROWS_FP64[wav], "double", 2), (dwt2.TILE_ROWS_FP64[wav], "double", 1)]
         for rows, t, nb in built:
             n = _find(counts, rf"k_fused_{direction}<{wid}, {rows}, {t}, {nb}>")
             per_body = table1 if nb == 2 else 2 * table1 - 1

@@ -54,12 +54,17 @@ def test_every_height_gives_the_same_bits(wav, norm):
                     torch.cuda.synchronize()
                     assert torch.equal(y, base), f"forward {what} rows {rows} buffers {nb} {order}"
                     assert torch.equal(z, back), f"inverse {what} rows {rows} buffers {nb} {order}"
-        for order in ("runs", "bands"):  # FP64 lifting, both orders
-            y = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), arithmetic="fp64",
-                             tile_order=order)
-            y0 = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), arithmetic="fp64")
-            torch.cuda.synchronize()
-            assert torch.equal(y, y0), f"fp64 forward {what} {order}"
+        y0 = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), arithmetic="fp64")
+        z0 = dwt2.inverse(y0, wav, lev, norm, out=empty_dev(h, w, pitch), arithmetic="fp64")
+        for order in ("runs", "bands"):  # FP64 lifting, both orders and bufferings
+            for nb in (1, 2):
+                y = dwt2.forward(xd, wav, lev, norm, out=empty_dev(h, w, pitch), arithmetic="fp64",
+                                 tile_order=order, lds_buffers=nb)
+                z = dwt2.inverse(y0, wav, lev, norm, out=empty_dev(h, w, pitch), arithmetic="fp64",
+                                 tile_order=order, lds_buffers=nb)
+                torch.cuda.synchronize()
+                assert torch.equal(y, y0), f"fp64 forward {what} {order} buffers {nb}"
+                assert torch.equal(z, z0), f"fp64 inverse {what} {order} buffers {nb}"
         if norm == "unit_dc":
             got = to_host(base)
             check(got, oracle.forward(x.astype(np.float64), wav, lev, norm),

@@ -52,7 +52,8 @@ def test_unbuilt_heights_are_rejected():
 def test_lds_buffering_option_is_validated():
     for bad in (-1, 3, 7):
         assert _fwd(dwt2.make_options(lds_buffers=bad)) == dwt2.E_UNSUPPORTED
-    assert _fwd(dwt2.make_options(arithmetic="fp64", lds_buffers=1)) == dwt2.E_UNSUPPORTED
+    # accepted (the aliased buffers then fail the call before any launch)
+    assert _fwd(dwt2.make_options(arithmetic="fp64", lds_buffers=1), dst=FAKE) == dwt2.E_ALIAS
     for scheme in ("sweldens", "rowcol", "monolithic*-tile", "explosive*"):
         assert _fwd(dwt2.make_options(scheme=scheme, lds_buffers=1)) == dwt2.E_UNSUPPORTED
         assert _fwd(dwt2.make_options(scheme=scheme, lds_buffers=2)) == dwt2.E_UNSUPPORTED
