@@ -306,7 +306,7 @@ def tile_table(dwt2, torch, x, y, z, reps, sizes=(8192, 2048, 512)):
 def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
     """Device time of one level per scheme (HIP-graph timed, as _graph_us)."""
     table = {}
-    for name in ("monolithic*", "monolithic*:fp64", "monolithic*:1buf", "monolithic*:fp64:1buf",
+    for name in ("monolithic*", "monolithic*:fp64", "monolithic*:1buf", "monolithic*:fp64:2buf",
                  "monolithic*-tile",
                  "monolithic", "sweldens",
                  "iwahashi", "iwahashi*", "explosive", "explosive*", "polyphase*", "rowcol",
@@ -314,7 +314,8 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
         name_w, _, wname = name.partition("@")
         scheme, _, variant = name_w.partition(":")
         arith = "fp64" if "fp64" in variant.split(":") else "auto"
-        nb = 1 if "1buf" in variant.split(":") else 0
+        parts = variant.split(":")
+        nb = 1 if "1buf" in parts else 2 if "2buf" in parts else 0
         wav_ = wname or wav
         ws = None
         st, nbytes = dwt2.dwt2_workspace_bytes(wav_, lev, xs[0].shape[1], xs[0].shape[0],
