@@ -306,7 +306,8 @@ def tile_table(dwt2, torch, x, y, z, reps, sizes=(8192, 2048, 512)):
 def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
     """Device time of one level per scheme (HIP-graph timed, as _graph_us)."""
     table = {}
-    for name in ("monolithic*", "monolithic*:fp64", "monolithic*:1buf", "monolithic*:fp64:2buf",
+    for name in ("monolithic*", "monolithic*:fp64", "monolithic*:1buf", "monolithic*:fp64:1buf",
+                 "monolithic*:fp64:2buf",
                  "monolithic*-tile",
                  "monolithic", "sweldens",
                  "iwahashi", "iwahashi*", "explosive", "explosive*", "polyphase*", "rowcol",

@@ -87,14 +87,16 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     return DWT2_OK;
 }
 
-// Default LDS buffering: double for FP32 lifting; single for FP64, whose
+// Default LDS buffering: double, except for the FP64 forward.  Its
 // double-buffered planes (36.9 KB at 9/7) would limit a CU to four
-// work-groups (measured: 8192^2 9/7 forward 130 us single against 138 double,
-// inverse equal).
-int buffers_of(const Config &c)
+// work-groups where its registers allow five (measured at 8192^2 9/7: 130 us
+// single against 138 double).  The FP64 inverse needs more registers and
+// fits four work-groups either way, so the extra barriers of single
+// buffering only cost it (139 us against 137).
+int buffers_of(const Config &c, bool inverse)
 {
     if (c.lds_buffers) return c.lds_buffers;
-    return c.arithmetic == DWT2_ARITH_FP64 ? 1 : 2;
+    return c.arithmetic == DWT2_ARITH_FP64 && !inverse ? 1 : 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -395,7 +397,7 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
             e = dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
             e = dwt2::launch_fused_forward(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
-                                           choose_rows(c.cfg, false, a.W, a.H), buffers_of(c.cfg),
+                                           choose_rows(c.cfg, false, a.W, a.H), buffers_of(c.cfg, false),
                                            choose_order(c.cfg, false, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
@@ -422,7 +424,7 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
             e = dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
             e = dwt2::launch_fused_inverse(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
-                                           choose_rows(c.cfg, true, a.W, a.H), buffers_of(c.cfg),
+                                           choose_rows(c.cfg, true, a.W, a.H), buffers_of(c.cfg, true),
                                            choose_order(c.cfg, true, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_inverse(c.cfg.wavelet, c.cfg.scheme, a, stream);
@@ -639,9 +641,9 @@ int time_level(bool inverse, const Checked &c, const void *args, int rows, int o
                hipEvent_t e0, hipEvent_t e1, hipStream_t stream, float *ms)
 {
     auto run = [&]() {
-        return inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg), order,
+        return inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg, inverse), order,
                                                     *(const dwt2::InvArgs *)args, stream)
-                       : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg), order,
+                       : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg, inverse), order,
                                                     *(const dwt2::FwdArgs *)args, stream);
     };
     hipError_t e = run();
