@@ -191,7 +191,20 @@ typedef DWT2_ENUM(dwt2_order) {
     DWT2_ORDER_BANDS = 2
 } dwt2_order;
 
-/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO, 0, 0, AUTO). */
+/*
+ * Fused multi-level tail of the MONOLITHIC_STAR kernel (fuse_tail = 1).  The
+ * levels whose input is at most 128 x 128 pixels, from the first such level
+ * on (when at least two remain), run in one work-group that keeps the LL
+ * bands between them in LDS: one launch instead of one per level.  The
+ * coefficients are bitwise those of the per-level launches.  The tail runs
+ * its tiles one after another (about 2.8 us each), while a launched level
+ * runs its tiles side by side: measured slower than the per-level launches
+ * for every image tried (64^2 to 1024^2), so off by default.  1 with FP64 arithmetic, another nonzero value, or a
+ * nonzero value with another scheme, the batched calls, dwt2_autotune or the
+ * server returns DWT2_E_UNSUPPORTED.
+ */
+
+/* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO, 0, 0, AUTO, 0). */
 typedef struct dwt2_options {
     int norm;        /* dwt2_norm */
     int scheme;      /* dwt2_scheme */
@@ -199,7 +212,8 @@ typedef struct dwt2_options {
     int tile_rows;   /* fused-kernel tile height (above); 0 = automatic */
     int lds_buffers; /* fused-kernel LDS buffering (above); 0 = double */
     int tile_order;  /* dwt2_order (above) */
-    int reserved[2]; /* must be zero */
+    int fuse_tail;   /* 1: fused multi-level tail (above); 0 = off */
+    int reserved[1]; /* must be zero */
 } dwt2_options;
 
 /*

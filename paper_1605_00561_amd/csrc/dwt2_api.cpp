@@ -37,6 +37,7 @@ struct Config {
     int wavelet, norm, scheme, arithmetic, tile_rows;
     int lds_buffers;  // 0 = default (2)
     int tile_order;   // 0 = automatic, else DWT2_ORDER_RUNS / DWT2_ORDER_BANDS
+    int fuse_tail;    // 1: levels from kTailSide x kTailSide down in one work-group
 };
 
 int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c)
@@ -51,6 +52,7 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     c->tile_rows = 0;
     c->lds_buffers = 0;
     c->tile_order = 0;
+    c->fuse_tail = 0;
     if (opt) {
         for (int r : opt->reserved)
             if (r != 0) return DWT2_E_ARG;
@@ -60,6 +62,7 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
         c->tile_rows = opt->tile_rows;
         c->lds_buffers = opt->lds_buffers;
         c->tile_order = opt->tile_order;
+        c->fuse_tail = opt->fuse_tail;
     }
     if (c->arithmetic < DWT2_ARITH_AUTO || c->arithmetic > DWT2_ARITH_FP64) return DWT2_E_UNSUPPORTED;
     if (c->norm != DWT2_NORM_UNIT_DC && c->norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
@@ -83,6 +86,10 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     if (c->tile_order != 0 &&
         (c->scheme != DWT2_SCHEME_MONOLITHIC_STAR ||
          (c->tile_order != DWT2_ORDER_RUNS && c->tile_order != DWT2_ORDER_BANDS)))
+        return DWT2_E_UNSUPPORTED;
+    // The fused multi-level tail: fused kernel, FP32 lifting.
+    if (c->fuse_tail != 0 &&
+        (c->fuse_tail != 1 || c->scheme != DWT2_SCHEME_MONOLITHIC_STAR || c->arithmetic == DWT2_ARITH_FP64))
         return DWT2_E_UNSUPPORTED;
     return DWT2_OK;
 }
@@ -316,6 +323,31 @@ dwt2::FwdArgs forward_level(const Checked &c, int k, const float *src, ptrdiff_t
 // Arguments of inverse level k: it rebuilds its W_k x H_k input from LL_{k+1}
 // (src at the last level, else its workspace buffer) and the details in src,
 // into dst (k = 0) or LL_k's buffer.
+// First level of the fused tail (c.levels when there is none): the first
+// level whose input is at most kTailSide on both sides, if at least two
+// levels remain from there.
+int tail_start(const Checked &c)
+{
+    if (!c.cfg.fuse_tail) return c.levels;
+    for (int k = 0; k + 1 < c.levels; k++)
+        if (c.ws[k] <= dwt2::kTailSide && c.hs[k] <= dwt2::kTailSide) return k;
+    return c.levels;
+}
+
+dwt2::TailArgs tail_args(const Checked &c, int k0, bool inverse)
+{
+    dwt2::TailArgs t;
+    t.W = c.ws[0];
+    t.H = c.hs[0];
+    t.k0 = k0;
+    t.levels = c.levels;
+    t.s = inverse ? inverse_scale(c.cfg.wavelet, c.cfg.norm) : level_scale(c.cfg.wavelet, c.cfg.norm);
+    t.ll_gain = c.cfg.norm == DWT2_NORM_PAPER ? 2.0f : 1.0f;
+    t.paper = c.cfg.norm == DWT2_NORM_PAPER;
+    t.buf_elems = dwt2::tail_buffer_elems(c.ws[0], c.hs[0], k0);
+    return t;
+}
+
 dwt2::InvArgs inverse_level(const Checked &c, int k, const float *src, ptrdiff_t src_pitch,
                             float *dst, ptrdiff_t dst_pitch, void *workspace)
 {
@@ -390,7 +422,8 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
     if (st != DWT2_OK) return st;
     char *wsb = (char *)workspace;
     float *tmp = (float *)(wsb + c.lay.t_off);
-    for (int k = 0; k < levels; k++) {
+    const int k0 = tail_start(c);
+    for (int k = 0; k < k0; k++) {
         const dwt2::FwdArgs a = forward_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
         hipError_t e;
         if (c.cfg.scheme == DWT2_SCHEME_ROWCOL)
@@ -401,6 +434,16 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
                                            choose_order(c.cfg, false, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    if (k0 < levels) {  // the remaining levels in one work-group
+        dwt2::TailArgs t = tail_args(c, k0, false);
+        const dwt2::FwdArgs a = forward_level(c, k0, src, src_pitch, dst, dst_pitch, workspace);
+        t.in = a.in;
+        t.in_pitch = a.in_pitch;
+        t.out = dst;
+        t.out_pitch = dst_pitch;
+        const hipError_t e = dwt2::launch_fused_tail_forward(c.cfg.wavelet, t, stream);
         if (e != hipSuccess) return hip_status(e);
     }
     return DWT2_OK;
@@ -417,7 +460,18 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
     if (st != DWT2_OK) return st;
     char *wsb = (char *)workspace;
     float *tmp = (float *)(wsb + c.lay.t_off);
-    for (int k = levels - 1; k >= 0; k--) {
+    const int k0 = tail_start(c);
+    if (k0 < levels) {  // the deepest levels in one work-group
+        dwt2::TailArgs t = tail_args(c, k0, true);
+        const dwt2::InvArgs a = inverse_level(c, k0, src, src_pitch, dst, dst_pitch, workspace);
+        t.in = src;
+        t.in_pitch = src_pitch;
+        t.out = a.out;
+        t.out_pitch = a.out_pitch;
+        const hipError_t e = dwt2::launch_fused_tail_inverse(c.cfg.wavelet, t, stream);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    for (int k = k0 - 1; k >= 0; k--) {
         const dwt2::InvArgs a = inverse_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
         hipError_t e;
         if (c.cfg.scheme == DWT2_SCHEME_ROWCOL)
@@ -482,7 +536,7 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
     int st = parse(DWT2_CDF53, ext, opt, &p->cfg);
     if (st != DWT2_OK) return st;
     if (p->cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || p->cfg.tile_rows != 0 || p->cfg.lds_buffers != 0 ||
-        p->cfg.tile_order != 0)
+        p->cfg.tile_order != 0 || p->cfg.fuse_tail != 0)
         return DWT2_E_UNSUPPORTED;
     p->rec.resize(count);
     p->buf_off[0].resize(count);
@@ -749,7 +803,7 @@ DWT2_EXPORT int dwt2_autotune(int inverse, dwt2_wavelet wavelet, int levels, int
                         workspace, workspace_bytes, &c);
     if (st != DWT2_OK) return st;
     if (c.cfg.scheme != DWT2_SCHEME_MONOLITHIC_STAR || c.cfg.arithmetic != DWT2_ARITH_FP32 ||
-        c.cfg.tile_rows != 0 || c.cfg.lds_buffers != 0 || c.cfg.tile_order != 0)
+        c.cfg.tile_rows != 0 || c.cfg.lds_buffers != 0 || c.cfg.tile_order != 0 || c.cfg.fuse_tail != 0)
         return DWT2_E_UNSUPPORTED;
     if (repeats < 1 || repeats > 1000) return DWT2_E_ARG;
     hipEvent_t e0 = nullptr, e1 = nullptr;

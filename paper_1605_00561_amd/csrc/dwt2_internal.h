@@ -154,6 +154,33 @@ hipError_t launch_fused_inverse(int wavelet, bool fp64, int rows, int buffers, i
 // below 2 or the height is not built).
 long long fused_tile_count(int wavelet, int rows, int W, int H);
 
+// Multi-level tail in one work-group: levels k0 .. levels - 1 of one image
+// (FP32, the wavelet's tallest built height, double-buffered planes), with
+// the LL bands between them kept in LDS.  Every tile runs the per-level
+// kernel's tile body, so the coefficients are bitwise those of the
+// per-level launches.  Forward: `in` is level k0's input (pitch in_pitch),
+// `out` the Mallat array.  Inverse: `in` is the Mallat array, `out` receives
+// level k0's output.  The LDS holds the planes and two LL buffers of
+// tail_buffer_elems(W, H, k0) floats each; kTailSide bounds level k0's sides
+// so that this stays within 64 KiB.
+constexpr int kTailSide = 128;
+struct TailArgs {
+    const float *in;
+    ptrdiff_t in_pitch;
+    float *out;
+    ptrdiff_t out_pitch;
+    int W, H;        // level-0 size of the image
+    int k0, levels;  // the tail's first level and the image's level count
+    Scale s;         // forward scales, or the inverse's reciprocals
+    float ll_gain;
+    int paper;       // centring quantum 2^k (PAPER) or 1
+    int buf_elems;   // floats per LDS LL buffer
+};
+int tail_buffer_elems(int W, int H, int k0);
+size_t tail_lds_bytes(int wavelet, int buf_elems);
+hipError_t launch_fused_tail_forward(int wavelet, const TailArgs &t, hipStream_t s);
+hipError_t launch_fused_tail_inverse(int wavelet, const TailArgs &t, hipStream_t s);
+
 // Batched fused launches.  One record per image, in device memory; a level
 // launch covers the tiles of every image that has that level.  The buffer
 // roles per level are those of the single-image level loop:

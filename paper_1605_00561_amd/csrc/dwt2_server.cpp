@@ -273,7 +273,8 @@ DWT2_EXPORT int dwt2_server_create(const dwt2_options *opt, const dwt2_server_co
     if (o.scheme != DWT2_SCHEME_AUTO && o.scheme != DWT2_SCHEME_MONOLITHIC_STAR)
         return DWT2_E_UNSUPPORTED;
     // batches run at their own height, double-buffered
-    if (o.tile_rows != 0 || o.lds_buffers != 0 || o.tile_order != 0) return DWT2_E_UNSUPPORTED;
+    if (o.tile_rows != 0 || o.lds_buffers != 0 || o.tile_order != 0 || o.fuse_tail != 0)
+        return DWT2_E_UNSUPPORTED;
     if (o.norm != DWT2_NORM_UNIT_DC && o.norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
     if (o.arithmetic < DWT2_ARITH_AUTO || o.arithmetic > DWT2_ARITH_FP64) return DWT2_E_UNSUPPORTED;
     int max_batch = 256, max_inflight = 2;

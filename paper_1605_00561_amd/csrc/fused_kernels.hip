@@ -565,6 +565,97 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_inverse(InvArgs a, int ntx, 
         inv_body<WAV, RB, T, false, NB>(a, sm, tc, tr, w, lane);
 }
 
+// Size of level k (0-based) of an n-sample side.
+__device__ __forceinline__ int level_size(int n, int k)
+{
+    return (int)(((long long)n + (1LL << k) - 1) >> k);
+}
+
+// Multi-level tail: one work-group runs levels k0 .. levels - 1 of one image,
+// tile after tile, with the LL bands between the levels in LDS (generic
+// pointers into the dynamic LDS: the tile body loads and stores them as it
+// does global memory).  Consecutive tiles reuse the planes without an extra
+// barrier: a tile's last plane reads come before the barrier that follows
+// the next tile's first publication.  A barrier separates the levels.
+template <int WAV>
+constexpr int tail_rows() { return kFusedRows[WAV][0] > kFusedRows[WAV][1] ? kFusedRows[WAV][0]
+                                  : kFusedRows[WAV][2] > kFusedRows[WAV][1] ? kFusedRows[WAV][2]
+                                                                            : kFusedRows[WAV][1]; }
+
+template <int WAV>
+__global__ __launch_bounds__(NTHREADS) void k_fused_tail_forward(TailArgs t)
+{
+    constexpr int RB = tail_rows<WAV>(), HQ = Halo<WAV>::HQ;
+    using G = Geo<WAV, RB>;
+    extern __shared__ float tail_lds[];
+    float *buf[2] = {tail_lds + G::PLANE_ELEMS, tail_lds + G::PLANE_ELEMS + t.buf_elems};
+    const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
+    for (int k = t.k0; k < t.levels; k++) {
+        const int W = level_size(t.W, k), H = level_size(t.H, k);
+        FwdArgs a;
+        a.in = k == t.k0 ? t.in : buf[(k - t.k0 - 1) & 1];
+        a.in_pitch = k == t.k0 ? t.in_pitch : ll_pitch(W);
+        a.ll = k == t.levels - 1 ? t.out : buf[(k - t.k0) & 1];
+        a.ll_pitch = k == t.levels - 1 ? t.out_pitch : ll_pitch((W + 1) / 2);
+        a.det = t.out;
+        a.det_pitch = t.out_pitch;
+        a.W = W;
+        a.H = H;
+        a.s = t.s;
+        a.ll_gain = t.ll_gain;
+        a.quantum = t.paper ? ldexpf(1.0f, k) : 1.0f;
+        const int ntx = ((W + 1) / 2 + G::IX - 1) / G::IX;
+        const int ntiles = (int)(ntx * (((H + 1) / 2 + G::IY - 1) / G::IY));
+        const bool aligned = (((uintptr_t)a.in | (uintptr_t)(a.in_pitch * 4)) & 7) == 0;
+        for (int tile = 0; tile < ntiles; tile++) {
+            const int tc = tile % ntx, tr = tile / ntx;
+            const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+            if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
+                fwd_body<WAV, RB, float, true>(a, tail_lds, tc, tr, w, lane);
+            else
+                fwd_body<WAV, RB, float, false>(a, tail_lds, tc, tr, w, lane);
+        }
+        __syncthreads();  // LL of level k is level k + 1's input
+    }
+}
+
+template <int WAV>
+__global__ __launch_bounds__(NTHREADS) void k_fused_tail_inverse(TailArgs t)
+{
+    constexpr int RB = tail_rows<WAV>(), HQ = Halo<WAV>::HQ;
+    using G = Geo<WAV, RB>;
+    extern __shared__ float tail_lds[];
+    float *buf[2] = {tail_lds + G::PLANE_ELEMS, tail_lds + G::PLANE_ELEMS + t.buf_elems};
+    const int lane = threadIdx.x & (TX - 1), w = threadIdx.x / TX;
+    for (int k = t.levels - 1; k >= t.k0; k--) {
+        const int W = level_size(t.W, k), H = level_size(t.H, k);
+        InvArgs a;
+        a.ll = k == t.levels - 1 ? t.in : buf[(k - t.k0) & 1];
+        a.ll_pitch = k == t.levels - 1 ? t.in_pitch : ll_pitch((W + 1) / 2);
+        a.det = t.in;
+        a.det_pitch = t.in_pitch;
+        a.out = k == t.k0 ? t.out : buf[(k - t.k0 - 1) & 1];
+        a.out_pitch = k == t.k0 ? t.out_pitch : ll_pitch(W);
+        a.W = W;
+        a.H = H;
+        a.inv_s = t.s;
+        a.ll_gain = t.ll_gain;
+        a.quantum = t.paper ? ldexpf(1.0f, k) : 1.0f;
+        const int ntx = ((W + 1) / 2 + G::IX - 1) / G::IX;
+        const int ntiles = (int)(ntx * (((H + 1) / 2 + G::IY - 1) / G::IY));
+        const bool aligned = (((uintptr_t)a.out | (uintptr_t)(a.out_pitch * 4)) & 7) == 0;
+        for (int tile = 0; tile < ntiles; tile++) {
+            const int tc = tile % ntx, tr = tile / ntx;
+            const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
+            if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
+                inv_body<WAV, RB, float, true>(a, tail_lds, tc, tr, w, lane);
+            else
+                inv_body<WAV, RB, float, false>(a, tail_lds, tc, tr, w, lane);
+        }
+        __syncthreads();  // level k's output is level k - 1's LL
+    }
+}
+
 // Batched levels.  A work-group finds its image by a search over the tile
 // starts that costs one coalesced load per 64-fold narrowing (two for up to
 // 4096 images), then runs the same tile body as the single-image kernel, so
@@ -584,11 +675,6 @@ __device__ __forceinline__ int find_image(const int *__restrict__ start, int cou
     return lo;
 }
 
-// Level-k geometry of image `im`: size, and the pointers of the level loop.
-__device__ __forceinline__ int level_size(int n, int k)
-{
-    return (int)(((long long)n + (1LL << k) - 1) >> k);
-}
 
 // One tile of image level `a`, given the tile's index within the image.
 template <int WAV, typename T>
@@ -830,6 +916,57 @@ long long fused_tile_count(int wavelet, int rows, int W, int H)
 {
     if (!fused_rows_supported(wavelet, false, rows)) return 0;
     return tile_count(halo_of(wavelet), NW * rows, W, H);
+}
+
+int tail_buffer_elems(int W, int H, int k0)
+{
+    // the largest LL band the tail keeps: level k0 + 1's input
+    const long long w = ((long long)W + (2LL << k0) - 1) >> (k0 + 1);
+    const long long h = ((long long)H + (2LL << k0) - 1) >> (k0 + 1);
+    return (int)(h * ll_pitch((int)w));
+}
+
+size_t tail_lds_bytes(int wavelet, int buf_elems)
+{
+    int planes = 0;
+    switch (wavelet) {
+    case CDF53: planes = Geo<CDF53, tail_rows<CDF53>()>::PLANE_ELEMS; break;
+    case CDF97: planes = Geo<CDF97, tail_rows<CDF97>()>::PLANE_ELEMS; break;
+    case DD137: planes = Geo<DD137, tail_rows<DD137>()>::PLANE_ELEMS; break;
+    default: return 0;
+    }
+    return sizeof(float) * ((size_t)planes + 2 * (size_t)buf_elems);
+}
+
+namespace {
+template <typename K>
+hipError_t launch_tail(K kern, int wavelet, const TailArgs &t, hipStream_t s)
+{
+    const size_t lds = tail_lds_bytes(wavelet, t.buf_elems);
+    if (lds == 0 || lds > 65536) return hipErrorInvalidValue;
+    void *argv[] = {(void *)&t};
+    return hipLaunchKernel((const void *)kern, dim3(1), dim3(NTHREADS), argv, lds, s);
+}
+}  // namespace
+
+hipError_t launch_fused_tail_forward(int wavelet, const TailArgs &t, hipStream_t s)
+{
+    switch (wavelet) {
+    case CDF53: return launch_tail(k_fused_tail_forward<CDF53>, wavelet, t, s);
+    case CDF97: return launch_tail(k_fused_tail_forward<CDF97>, wavelet, t, s);
+    case DD137: return launch_tail(k_fused_tail_forward<DD137>, wavelet, t, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fused_tail_inverse(int wavelet, const TailArgs &t, hipStream_t s)
+{
+    switch (wavelet) {
+    case CDF53: return launch_tail(k_fused_tail_inverse<CDF53>, wavelet, t, s);
+    case CDF97: return launch_tail(k_fused_tail_inverse<CDF97>, wavelet, t, s);
+    case DD137: return launch_tail(k_fused_tail_inverse<DD137>, wavelet, t, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_batch_forward(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s)

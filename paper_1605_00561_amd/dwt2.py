@@ -59,7 +59,8 @@ ARITHS = {"auto": ARITH_AUTO, "fp32": ARITH_FP32, "fp64": ARITH_FP64,
 class Options(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_int), ("scheme", ctypes.c_int), ("arithmetic", ctypes.c_int),
                 ("tile_rows", ctypes.c_int), ("lds_buffers", ctypes.c_int),
-                ("tile_order", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("tile_order", ctypes.c_int), ("fuse_tail", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1)]
 
 
 class Image(ctypes.Structure):
@@ -158,7 +159,7 @@ def library() -> ctypes.CDLL:
 
 
 def make_options(norm="unit_dc", scheme="auto", arithmetic="auto", tile_rows=0,
-                 lds_buffers=0, tile_order="auto") -> Options:
+                 lds_buffers=0, tile_order="auto", fuse_tail=0) -> Options:
     o = Options()
     o.norm = NORMS[norm]
     o.scheme = SCHEMES[scheme]
@@ -166,6 +167,7 @@ def make_options(norm="unit_dc", scheme="auto", arithmetic="auto", tile_rows=0,
     o.tile_rows = int(tile_rows)
     o.lds_buffers = int(lds_buffers)
     o.tile_order = ORDERS[tile_order] if tile_order in ORDERS else int(tile_order)
+    o.fuse_tail = int(fuse_tail)
     return o
 
 
@@ -343,7 +345,7 @@ def _stream_handle(stream):
 
 
 def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, arithmetic,
-               tile_rows, lds_buffers=0, tile_order="auto"):
+               tile_rows, lds_buffers=0, tile_order="auto", fuse_tail=0):
     """Allocate out / workspace as needed and run call(opt, ws, ws_bytes) -> status,
     a closure over the C entry point with the tensors' pointers."""
     import torch
@@ -352,7 +354,7 @@ def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, ari
     if out is None:
         out = torch.empty((h, w), dtype=torch.float32, device=x.device)
     _check_image(out)
-    opt = make_options(norm, scheme, arithmetic, tile_rows, lds_buffers, tile_order)
+    opt = make_options(norm, scheme, arithmetic, tile_rows, lds_buffers, tile_order, fuse_tail)
     ws, nws = _workspace(wavelet, levels, w, h, opt, x.device, workspace)
     st = call(out, opt, ws.data_ptr() if ws is not None else None, nws)
     if st != OK:
@@ -362,26 +364,26 @@ def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, ari
 
 def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
             workspace=None, stream=None, arithmetic="auto", tile_rows=0, lds_buffers=0,
-            tile_order="auto"):
+            tile_order="auto", fuse_tail=0):
     """Forward DWT of a (H, W) float32 device tensor; returns the Mallat layout."""
     def call(y, opt, ws, nws):
         return dwt2_forward(wavelet, levels, img.shape[1], img.shape[0], img.data_ptr(),
                             img.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                             nws, _stream_handle(stream))
     return _transform("dwt2_forward", call, img, wavelet, levels, norm, scheme, out, workspace,
-                      arithmetic, tile_rows, lds_buffers, tile_order)
+                      arithmetic, tile_rows, lds_buffers, tile_order, fuse_tail)
 
 
 def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
             workspace=None, stream=None, arithmetic="auto", tile_rows=0, lds_buffers=0,
-            tile_order="auto"):
+            tile_order="auto", fuse_tail=0):
     """Inverse DWT of a (H, W) Mallat-layout float32 device tensor; returns the image."""
     def call(y, opt, ws, nws):
         return dwt2_inverse(wavelet, levels, coef.shape[1], coef.shape[0], coef.data_ptr(),
                             coef.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                             nws, _stream_handle(stream))
     return _transform("dwt2_inverse", call, coef, wavelet, levels, norm, scheme, out, workspace,
-                      arithmetic, tile_rows, lds_buffers, tile_order)
+                      arithmetic, tile_rows, lds_buffers, tile_order, fuse_tail)
 
 
 def autotune(x, wavelet="cdf53", levels=1, inverse=False, norm="unit_dc", repeats=20, out=None,

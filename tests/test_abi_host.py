@@ -103,7 +103,7 @@ def test_argument_errors():
     assert _fwd(dst_pitch=8) == dwt2.E_ARG
     assert _fwd(src=FAKE + 2) == dwt2.E_ARG  # not 4-byte aligned
     o = dwt2.make_options()
-    o.reserved[1] = 1
+    o.reserved[0] = 1
     assert _fwd(opt=o) == dwt2.E_ARG
 
 

@@ -99,7 +99,7 @@ def test_options_errors():
                         (dict(lds_buffers=1), dwt2.E_UNSUPPORTED)]:
         assert both(a, n, opt=dwt2.make_options(**opt)) == [status] * 2
     o = dwt2.make_options()
-    o.reserved[1] = 1
+    o.reserved[0] = 1
     assert both(a, n, opt=o) == [dwt2.E_ARG] * 2
     o = dwt2.make_options()
     o.norm = 9

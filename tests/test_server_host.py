@@ -30,6 +30,7 @@ def test_create_argument_errors():
     assert create(opt=dwt2.make_options(tile_rows=3)) == dwt2.E_UNSUPPORTED
     assert create(opt=dwt2.make_options(lds_buffers=1)) == dwt2.E_UNSUPPORTED
     assert create(opt=dwt2.make_options(tile_order="bands")) == dwt2.E_UNSUPPORTED
+    assert create(opt=dwt2.make_options(fuse_tail=1)) == dwt2.E_UNSUPPORTED
     o = dwt2.make_options()
     o.norm = 5
     assert create(opt=o) == dwt2.E_UNSUPPORTED

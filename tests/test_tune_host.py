@@ -58,7 +58,7 @@ def test_lds_buffering_option_is_validated():
         assert _fwd(dwt2.make_options(scheme=scheme, lds_buffers=1)) == dwt2.E_UNSUPPORTED
         assert _fwd(dwt2.make_options(scheme=scheme, lds_buffers=2)) == dwt2.E_UNSUPPORTED
     o = dwt2.make_options(lds_buffers=1)
-    o.reserved[1] = 1
+    o.reserved[0] = 1
     assert _fwd(o) == dwt2.E_ARG
 
 
@@ -325,3 +325,25 @@ def test_tuning_file_keeps_the_order(tmp_path):
     assert dwt2.load_tuning(path, arch="gfx950") == 2
     assert dwt2.tile_order("cdf97", 16384, 16384) == "bands"
     assert dwt2.tile_rows("cdf97", 16384, 16384) == 4
+
+
+# --- fused multi-level tail -----------------------------------------------------
+
+def test_fuse_tail_option_validation():
+    """dst == src makes every call an error after option parsing (DWT2_E_ALIAS
+    means the options were accepted); nothing is launched."""
+    assert _fwd(dwt2.make_options(fuse_tail=1), dst=FAKE) == dwt2.E_ALIAS
+    assert _fwd(dwt2.make_options(fuse_tail=1, tile_rows=2, tile_order="bands"), dst=FAKE) == \
+        dwt2.E_ALIAS
+    for bad in (2, -1):
+        assert _fwd(dwt2.make_options(fuse_tail=bad), dst=FAKE) == dwt2.E_UNSUPPORTED
+    assert _fwd(dwt2.make_options(fuse_tail=1, arithmetic="fp64"), dst=FAKE) == dwt2.E_UNSUPPORTED
+    for scheme in ("sweldens", "rowcol", "explosive*"):
+        assert _fwd(dwt2.make_options(scheme=scheme, fuse_tail=1), dst=FAKE) == dwt2.E_UNSUPPORTED
+    o = dwt2.make_options(fuse_tail=1)
+    lib = dwt2.library()
+    assert lib.dwt2_autotune(0, 1, 1, 16, 16, FAKE, 16, FAKE + (1 << 24), 16, 0, ctypes.byref(o),
+                             None, 0, 5, None) == dwt2.E_UNSUPPORTED
+    arr = (dwt2.Image * 1)(dwt2.Image(1, 1, 64, 64, FAKE, 64, FAKE + (1 << 24), 64))
+    st, _ = dwt2.dwt2_batch_workspace_bytes(arr, 1, o)
+    assert st == dwt2.E_UNSUPPORTED
