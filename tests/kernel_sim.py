@@ -222,17 +222,21 @@ def _tiles(wav, rb, w, h):
     return hq, ix, iy, -(-qw // ix), -(-qh // iy)
 
 
-def forward(img, wav, rb, nb=2, dtype=np.float64, barriers=None):
-    """One forward level (UNIT_DC) of the modelled kernel: Mallat layout."""
+def forward(img, wav, rb, nb=2, dtype=np.float64, barriers=None, shared_planes=False):
+    """One forward level (UNIT_DC) of the modelled kernel: Mallat layout.
+    shared_planes: one work-group runs the tiles one after another on the
+    same planes, with no barrier between tiles (the fused multi-level tail);
+    the race checker then spans the tiles."""
     h, w = img.shape
     img = img.astype(dtype)
     sll, shh = (dtype(v) for v in unit_dc_scales(wav))
     hq, ix, iy, ntx, nty = _tiles(wav, rb, w, h)
     qw, qh = (w + 1) // 2, (h + 1) // 2
     out = np.full((h, w), np.nan)
+    shared = Tile(wav, rb, nb, dtype, barriers) if shared_planes else None
     for tr in range(nty):
         for tc in range(ntx):
-            t = Tile(wav, rb, nb, dtype, barriers)
+            t = shared if shared is not None else Tile(wav, rb, nb, dtype, barriers)
             qc = tc * ix - hq + np.arange(TX)
             x0 = np.array([mirror(2 * c, w) for c in qc])
             x1 = np.array([mirror(2 * c + 1, w) for c in qc])
@@ -268,17 +272,19 @@ def forward(img, wav, rb, nb=2, dtype=np.float64, barriers=None):
     return out
 
 
-def inverse(coef, wav, rb, nb=2, dtype=np.float64, barriers=None):
-    """One inverse level (UNIT_DC) of the modelled kernel: the image."""
+def inverse(coef, wav, rb, nb=2, dtype=np.float64, barriers=None, shared_planes=False):
+    """One inverse level (UNIT_DC) of the modelled kernel: the image
+    (shared_planes as for forward)."""
     h, w = coef.shape
     coef = coef.astype(dtype)
     sll, shh = (dtype(v) for v in unit_dc_scales(wav))
     hq, ix, iy, ntx, nty = _tiles(wav, rb, w, h)
     qw, qh = (w + 1) // 2, (h + 1) // 2
     out = np.full((h, w), np.nan)
+    shared = Tile(wav, rb, nb, dtype, barriers) if shared_planes else None
     for tr in range(nty):
         for tc in range(ntx):
-            t = Tile(wav, rb, nb, dtype, barriers)
+            t = shared if shared is not None else Tile(wav, rb, nb, dtype, barriers)
             qc = tc * ix - hq + np.arange(TX)
             cl = np.array([mirror(2 * c, w) >> 1 for c in qc])
             ch = np.array([mirror(2 * c + 1, w) >> 1 for c in qc])

@@ -1,8 +1,10 @@
 """CPU checks of the fused kernel's tile algorithm through its model
 (tests/kernel_sim.py): the result equals the oracle, the barrier schedule is
 free of LDS races for double and single buffering (and removing any one of
-its barriers is caught), unwritten LDS never reaches a stored output, and
-every tile height gives the same bits."""
+its barriers is caught), unwritten LDS never reaches a stored output, every
+tile height gives the same bits, and consecutive tiles may share the
+double-buffered planes without a barrier between them (the fused
+multi-level tail), which single-buffered planes may not."""
 import numpy as np
 import pytest
 
@@ -76,3 +78,27 @@ def test_heights_and_bufferings_give_identical_fp32_bits(wav):
             for rb in ROWS[wav] for nb in (2, 1)]
     for o in invs[1:]:
         assert np.array_equal(o, invs[0])
+
+
+@pytest.mark.parametrize("wav", ["cdf53", "cdf97", "dd137"])
+def test_consecutive_tiles_share_double_buffered_planes(wav):
+    """One work-group running a level's tiles back to back on the same
+    planes (no barrier between tiles) is race-free and gives the oracle's
+    result, in both directions, at the tallest height (the tail's)."""
+    x = image(130, 70, 720)
+    rb = ROWS[wav][-1]
+    y = ks.forward(x, wav, rb, 2, shared_planes=True)
+    assert np.abs(y - oracle.forward(x, wav, 1)).max() < 1e-9
+    z = ks.inverse(y, wav, rb, 2, shared_planes=True)
+    assert np.abs(z - oracle.inverse(y, wav, 1)).max() < 1e-9
+
+
+@pytest.mark.parametrize("direction", ["forward", "inverse"])
+def test_single_buffered_planes_need_a_barrier_between_tiles(direction):
+    """With one plane buffer, the next tile's first publication overwrites
+    rows the previous tile's last step still reads in the same epoch."""
+    x = image(130, 70, 721)
+    arg = x if direction == "forward" else ks.forward(x, "cdf97", 4, 2)
+    run = ks.forward if direction == "forward" else ks.inverse
+    with pytest.raises(ks.Race):
+        run(arg, "cdf97", 4, 1, shared_planes=True)
