@@ -92,3 +92,13 @@ def test_rowcol_kernels_have_no_barriers(counts):
     for k, v in counts.items():
         if "k_rows_" in k or "k_cols_" in k:
             assert v == 0, k
+
+
+@pytest.mark.parametrize("direction", ["forward", "inverse"])
+def test_fused_tail_kernels_add_one_barrier_per_level(counts, direction):
+    """The fused multi-level tail inlines the double-buffered tile body twice
+    (Table 1's count each) plus the one barrier between levels."""
+    for wid, wav in WAVELET_IDS.items():
+        table1 = TABLE1[(wav, "monolithic*")][0]
+        n = _find(counts, rf"k_fused_tail_{direction}<{wid}>")
+        assert n == 2 * table1 + 1, (direction, wav, n)
