@@ -91,7 +91,8 @@ typedef DWT2_ENUM(dwt2_ext) { DWT2_EXT_WHOLE_SYMMETRIC = 0 } dwt2_ext;
  * per axis (Sec. 2; zeta = sqrt(2) for 5/3, 1.14960439886... for 9/7):
  * LL * zeta^2, HH / zeta^2 (DD 13/7: the paper gives no zeta; sqrt(2) as for
  * 5/3).  UNIT_DC scales so that a constant image keeps its value in LL (5/3
- * and DD 13/7: no scaling; 9/7: LL / K^2, HH * K^2 with K = 1.23017410491...).  Per level k the two differ by exact powers of two:
+ * and DD 13/7: no scaling; 9/7: LL / K^2, HH * K^2 with K = 1.23017410491...).
+ * Per level k the two differ by exact powers of two:
  * PAPER = UNIT_DC * 2^(k-1) * {2 for LL, 1 for HL and LH, 1/2 for HH}.
  */
 typedef DWT2_ENUM(dwt2_norm) { DWT2_NORM_UNIT_DC = 0, DWT2_NORM_PAPER = 1 } dwt2_norm;
@@ -199,9 +200,10 @@ typedef DWT2_ENUM(dwt2_order) {
  * coefficients are bitwise those of the per-level launches.  The tail runs
  * its tiles one after another (about 2.8 us each), while a launched level
  * runs its tiles side by side: measured slower than the per-level launches
- * for every image tried (64^2 to 1024^2), so off by default.  1 with FP64 arithmetic, another nonzero value, or a
- * nonzero value with another scheme, the batched calls, dwt2_autotune or the
- * server returns DWT2_E_UNSUPPORTED.
+ * for every image tried (64^2 to 1024^2), so it is off by default.
+ * DWT2_E_UNSUPPORTED for fuse_tail = 1 with FP64 arithmetic or with another
+ * scheme, for any value other than 0 and 1, and for a nonzero value passed
+ * to the batched calls, dwt2_autotune or the server.
  */
 
 /* Optional settings; pass NULL for defaults (UNIT_DC, AUTO, AUTO, 0, 0, AUTO, 0). */
@@ -226,7 +228,11 @@ int dwt2_workspace_bytes(dwt2_wavelet wavelet, int levels, int width, int height
 
 /*
  * Forward transform: src is a width x height image (pitch src_pitch), dst
- * receives the Mallat layout of `levels` levels (pitch dst_pitch).
+ * receives the Mallat layout of `levels` levels (pitch dst_pitch).  One level
+ * is the separable 2-D decomposition into LL, HL, LH and HH of Sec. 1 and of
+ * Sec. 2 ("Discrete Wavelet Transform": Mallat's pyramid, each level applied
+ * to the previous LL); the default scheme computes it with the Monolithic*
+ * steps of Sec. 4 ("Improvements"), the others with their sections' steps.
  * workspace: device memory of at least dwt2_workspace_bytes() bytes (may be
  * NULL when that is 0), not overlapping src or dst.
  */
@@ -238,7 +244,12 @@ int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int height,
 /*
  * Inverse transform: src holds the Mallat layout produced by dwt2_forward
  * with the same wavelet, levels, sizes and normalisation; dst receives the
- * width x height image.  Same argument rules as dwt2_forward.
+ * width x height image.  The paper gives the forward direction only; each
+ * level undoes the forward level's steps in reverse order with negated
+ * lifting coefficients and reciprocal scales (every lifting step of Sec. 2,
+ * "Lifting Scheme", is inverted by subtracting what it added), so the
+ * Monolithic* inverse keeps the two barriers per lifting pair of Sec. 4.
+ * Same argument rules as dwt2_forward.
  */
 int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int height,
                  const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
@@ -302,10 +313,12 @@ int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext ext,
  * forms each batch from the requests pending at that moment (first come,
  * first served, at most max_batch), as long as fewer than max_inflight
  * batches are enqueued and not finished; so under light load a request is
- * launched at once, and under heavy load batches grow.  Admission is by
+ * launched at once, and under heavy load batches grow.  Admission is by HBM
  * footprint: a batch's workspace (image table + each image's LL buffers)
  * is carved from the caller's device arena, and a request waits while the
- * arena is full.  A completion thread retires finished batches (in stream
+ * arena is full; with max_footprint_mib set, a request also waits while the
+ * requests in flight plus it would touch more than that many bytes of device
+ * memory, counting each request's input and output spans and its LL buffers.  A completion thread retires finished batches (in stream
  * order) and records each request's latency (submission to observed
  * completion, host clock).
  *
@@ -333,9 +346,11 @@ typedef struct dwt2_request {
 } dwt2_request;
 
 typedef struct dwt2_server_config {
-    int max_batch;    /* requests per batch, 1..DWT2_BATCH_MAX (0 = 256) */
-    int max_inflight; /* batches enqueued and not finished, >= 1 (0 = 2) */
-    int reserved[6];  /* must be zero */
+    int max_batch;         /* requests per batch, 1..DWT2_BATCH_MAX (0 = 256) */
+    int max_inflight;      /* batches enqueued and not finished, >= 1 (0 = 2) */
+    int max_footprint_mib; /* cap on the HBM footprint of the requests in flight, MiB
+                              (0 = no cap beyond the arena) */
+    int reserved[5];       /* must be zero */
 } dwt2_server_config;
 
 typedef struct dwt2_completion {
@@ -356,8 +371,9 @@ int dwt2_server_create(const dwt2_options *opt, const dwt2_server_config *cfg, v
 /*
  * Queue one request; returns at once.  The request is validated as by
  * dwt2_forward (status returned, nothing queued); a request whose workspace
- * alone exceeds the arena gives DWT2_E_WORKSPACE, one overlapping the arena
- * DWT2_E_ALIAS.  *ticket identifies it for dwt2_server_wait.
+ * alone exceeds the arena, or whose footprint alone exceeds the footprint
+ * cap, gives DWT2_E_WORKSPACE, one overlapping the arena DWT2_E_ALIAS.
+ * *ticket identifies it for dwt2_server_wait.
  */
 int dwt2_server_submit(dwt2_server *server, const dwt2_request *request,
                        unsigned long long *ticket);

@@ -320,9 +320,6 @@ dwt2::FwdArgs forward_level(const Checked &c, int k, const float *src, ptrdiff_t
     return a;
 }
 
-// Arguments of inverse level k: it rebuilds its W_k x H_k input from LL_{k+1}
-// (src at the last level, else its workspace buffer) and the details in src,
-// into dst (k = 0) or LL_k's buffer.
 // First level of the fused tail (c.levels when there is none): the first
 // level whose input is at most kTailSide on both sides, if at least two
 // levels remain from there.
@@ -348,6 +345,9 @@ dwt2::TailArgs tail_args(const Checked &c, int k0, bool inverse)
     return t;
 }
 
+// Arguments of inverse level k: it rebuilds its W_k x H_k input from LL_{k+1}
+// (src at the last level, else its workspace buffer) and the details in src,
+// into dst (k = 0) or LL_k's buffer.
 dwt2::InvArgs inverse_level(const Checked &c, int k, const float *src, ptrdiff_t src_pitch,
                             float *dst, ptrdiff_t dst_pitch, void *workspace)
 {

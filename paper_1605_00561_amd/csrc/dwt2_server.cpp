@@ -16,6 +16,12 @@
 // A completer waits for the oldest batch's event, stamps its requests and
 // frees its arena block.
 //
+// Admission is by HBM footprint: a batch's workspace must fit a free block of
+// the arena, and, when the caller sets a footprint cap, the requests in
+// flight (launched, not yet retired) may together touch at most that many
+// bytes of device memory, counting each request's input, output and LL
+// buffers.
+//
 // The arena is a caller-owned device buffer; the server keeps only a host-side
 // free list over it (first fit, coalescing), so nothing is allocated on the
 // device.
@@ -63,6 +69,16 @@ struct Pending {
     Clock::time_point submitted;
 };
 
+dwt2::serve::Item item_of(const Pending &p)
+{
+    const uintptr_t s0 = (uintptr_t)p.r.src, d0 = (uintptr_t)p.r.dst;
+    dwt2::serve::Item it{s0, s0 + span_bytes(p.r.src_pitch, p.r.width, p.r.height), d0,
+                         d0 + span_bytes(p.r.dst_pitch, p.r.width, p.r.height),
+                         p.r.inverse, p.r.levels, p.ll_bytes, 0};
+    it.footprint = dwt2::serve::footprint_of(it);
+    return it;
+}
+
 struct Flight {
     hipEvent_t ev = nullptr;
     std::vector<unsigned long long> tickets;
@@ -70,6 +86,7 @@ struct Flight {
     std::vector<int> status;
     Clock::time_point launched;
     size_t off = 0, bytes = 0;
+    size_t footprint = 0;  // input + output + LL bytes of its requests
 };
 
 size_t table_bytes(int count, int lmax) { return dwt2::batch_table_bytes(count, lmax); }
@@ -79,6 +96,8 @@ size_t table_bytes(int count, int lmax) { return dwt2::batch_table_bytes(count, 
 struct dwt2_server {
     dwt2_options opt{};
     int max_batch = 256, max_inflight = 2;
+    size_t footprint_cap = SIZE_MAX;  // bytes; SIZE_MAX: no cap
+    size_t in_flight_footprint = 0;
     char *arena = nullptr;
     size_t arena_bytes = 0;
     hipStream_t stream = nullptr;
@@ -115,25 +134,23 @@ void dwt2_server::schedule()
 
         // Take the longest admissible prefix of the pending queue.
         Group g[2];
-        auto item = [&](size_t i) {
-            const Pending &p = pending[i];
-            const uintptr_t s0 = (uintptr_t)p.r.src, d0 = (uintptr_t)p.r.dst;
-            return dwt2::serve::Item{s0, s0 + span_bytes(p.r.src_pitch, p.r.width, p.r.height), d0,
-                                     d0 + span_bytes(p.r.dst_pitch, p.r.width, p.r.height),
-                                     p.r.inverse, p.r.levels, p.ll_bytes};
-        };
-        const size_t n = dwt2::serve::next_batch(item, pending.size(), max_batch, space, table_bytes, g);
+        size_t fp = 0;
+        auto item = [&](size_t i) { return item_of(pending[i]); };
+        const size_t n = dwt2::serve::next_batch(item, pending.size(), max_batch, space,
+                                                 footprint_cap - in_flight_footprint, table_bytes, g, &fp);
         if (n == 0) {
             if (inflight.empty()) {
                 // Unreachable: submission rejects a request larger than the
-                // whole arena, and with nothing in flight the arena is free.
+                // whole arena or the footprint cap, and with nothing in
+                // flight both are free.
                 const Pending p = pending.front();
                 pending.pop_front();
                 done[p.ticket] = {DWT2_E_WORKSPACE, 0.0, us_between(p.submitted, Clock::now())};
                 cv_done.notify_all();
                 continue;
             }
-            // The head does not fit the free arena: wait for a batch to retire.
+            // The head does not fit the free arena or the footprint budget:
+            // wait for a batch to retire.
             const unsigned long long seen = retired;
             cv_sched.wait(lk, [&] { return retired != seen; });
             continue;
@@ -141,6 +158,8 @@ void dwt2_server::schedule()
         Flight f;
         f.bytes = group_bytes(g[0], table_bytes) + group_bytes(g[1], table_bytes);
         f.off = space.alloc(f.bytes);
+        f.footprint = fp;
+        in_flight_footprint += fp;
         std::vector<Pending> take(pending.begin(), pending.begin() + n);
         pending.erase(pending.begin(), pending.begin() + n);
         if (!events.empty()) {
@@ -229,6 +248,7 @@ void dwt2_server::complete()
             done[f.tickets[i]] = c;
         }
         space.release(f.off, f.bytes);
+        in_flight_footprint -= f.footprint;
         if (f.ev) events.push_back(f.ev);
         retired++;
         cv_done.notify_all();
@@ -255,6 +275,7 @@ int request_footprint(const dwt2_server *s, const dwt2_request *r, size_t *ll_by
     const uintptr_t a1 = a0 + s->arena_bytes;
     if ((s0 < d1 && d0 < s1) || (s0 < a1 && a0 < s1) || (d0 < a1 && a0 < d1)) return DWT2_E_ALIAS;
     if (one > s->arena_bytes) return DWT2_E_WORKSPACE;
+    if ((s1 - s0) + (d1 - d0) + *ll_bytes > s->footprint_cap) return DWT2_E_WORKSPACE;
     return DWT2_OK;
 }
 
@@ -278,13 +299,16 @@ DWT2_EXPORT int dwt2_server_create(const dwt2_options *opt, const dwt2_server_co
     if (o.norm != DWT2_NORM_UNIT_DC && o.norm != DWT2_NORM_PAPER) return DWT2_E_UNSUPPORTED;
     if (o.arithmetic < DWT2_ARITH_AUTO || o.arithmetic > DWT2_ARITH_FP64) return DWT2_E_UNSUPPORTED;
     int max_batch = 256, max_inflight = 2;
+    size_t footprint_cap = SIZE_MAX;
     if (cfg) {
         for (int r : cfg->reserved)
             if (r) return DWT2_E_ARG;
-        if (cfg->max_batch < 0 || cfg->max_batch > DWT2_BATCH_MAX || cfg->max_inflight < 0)
+        if (cfg->max_batch < 0 || cfg->max_batch > DWT2_BATCH_MAX || cfg->max_inflight < 0 ||
+            cfg->max_footprint_mib < 0)
             return DWT2_E_ARG;
         if (cfg->max_batch) max_batch = cfg->max_batch;
         if (cfg->max_inflight) max_inflight = cfg->max_inflight;
+        if (cfg->max_footprint_mib) footprint_cap = (size_t)cfg->max_footprint_mib << 20;
     }
     if (!arena || arena_bytes < kAlign) return DWT2_E_WORKSPACE;
     if ((uintptr_t)arena & (kAlign - 1)) return DWT2_E_ARG;
@@ -295,6 +319,7 @@ DWT2_EXPORT int dwt2_server_create(const dwt2_options *opt, const dwt2_server_co
     s->opt = o;
     s->max_batch = max_batch;
     s->max_inflight = max_inflight;
+    s->footprint_cap = footprint_cap;
     s->arena = (char *)arena;
     s->arena_bytes = arena_bytes / kAlign * kAlign;
     s->space = Arena(s->arena_bytes);

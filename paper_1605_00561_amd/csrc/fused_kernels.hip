@@ -24,7 +24,8 @@
 //     visible.  Two plane buffers alternate between predict and update, so
 //     Monolithic* keeps its two barriers per lifting pair (double buffering;
 //     single buffering, NB = 1, adds one barrier per step, Sec. 6).
-// LDS is at most 29 KB (FP32), so occupancy is set by registers.
+// The per-level kernels use at most 29 KB of LDS (FP32), so occupancy is set
+// by registers; the multi-level tail adds its LL buffers, up to 60 KB.
 //
 // Borders: whole-sample symmetric extension, samples read from mirrored
 // positions.  Centring: each tile subtracts a rounded local mean c from its

@@ -92,13 +92,21 @@ public:
 };
 
 // One pending request as the scheduler sees it: the byte ranges it reads and
-// writes, its direction and depth, and the bytes of its own LL buffers in a
-// batched call's workspace.
+// writes, its direction and depth, the bytes of its own LL buffers in a
+// batched call's workspace, and its HBM footprint (the bytes of its input,
+// its output and its LL buffers).
 struct Item {
     uintptr_t src_lo, src_hi, dst_lo, dst_hi;
     int inverse, levels;
     size_t ll_bytes;
+    size_t footprint;
 };
+
+// HBM footprint of a request: input span + output span + LL buffers.
+inline size_t footprint_of(const Item &it)
+{
+    return (size_t)(it.src_hi - it.src_lo) + (size_t)(it.dst_hi - it.dst_lo) + it.ll_bytes;
+}
 
 // Workspace of one direction's batched call: table + the images' LL buffers.
 struct Group {
@@ -115,16 +123,19 @@ size_t group_bytes(const Group &g, Table table)
 // The next batch: the longest prefix of the pending items, in submission
 // order and of at most max_batch items, in which no item reads or writes a
 // range that an earlier item of the prefix writes, nor writes a range that an
-// earlier item reads (such an item must run after the batch), and whose two
-// direction groups fit one free block of the arena together.  item(i) gives
-// the i-th pending item; table(count, lmax) the table bytes of a batched
-// call.  Writes the groups and returns the prefix length (0: the first item
-// does not fit the free arena).
+// earlier item reads (such an item must run after the batch), whose two
+// direction groups fit one free block of the arena together, and whose
+// footprints sum to at most `budget` bytes (the footprint cap less what the
+// batches in flight hold).  item(i) gives the i-th pending item;
+// table(count, lmax) the table bytes of a batched call.  Writes the groups
+// and the batch's footprint and returns the prefix length (0: the first item
+// does not fit the free arena or the budget).
 template <typename ItemAt, typename Table>
-size_t next_batch(ItemAt item, size_t pending, int max_batch, const Arena &arena, Table table,
-                  Group g[2])
+size_t next_batch(ItemAt item, size_t pending, int max_batch, const Arena &arena, size_t budget,
+                  Table table, Group g[2], size_t *footprint)
 {
     g[0] = g[1] = Group{};
+    *footprint = 0;
     RangeSet written, read;
     size_t n = 0;
     for (; n < pending && (long long)n < max_batch; n++) {
@@ -132,6 +143,7 @@ size_t next_batch(ItemAt item, size_t pending, int max_batch, const Arena &arena
         if (written.overlaps(it.src_lo, it.src_hi) || written.overlaps(it.dst_lo, it.dst_hi) ||
             read.overlaps(it.dst_lo, it.dst_hi))
             break;
+        if (it.footprint > budget - *footprint) break;
         Group t[2] = {g[0], g[1]};
         Group &k = t[it.inverse ? 1 : 0];
         k.count++;
@@ -140,6 +152,7 @@ size_t next_batch(ItemAt item, size_t pending, int max_batch, const Arena &arena
         if (!arena.fits(group_bytes(t[0], table) + group_bytes(t[1], table))) break;
         g[0] = t[0];
         g[1] = t[1];
+        *footprint += it.footprint;
         written.insert(it.dst_lo, it.dst_hi);
         read.insert(it.src_lo, it.src_hi);
     }

@@ -80,7 +80,7 @@ class Request(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int), ("max_inflight", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("max_footprint_mib", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class Completion(ctypes.Structure):
@@ -344,18 +344,30 @@ def _stream_handle(stream):
     return s.cuda_stream
 
 
+def _on_stream(stream):
+    """Context in which torch allocates for work enqueued on `stream`: the
+    caching allocator then keeps those blocks until that stream's work has
+    passed them, instead of handing them to the current stream's next
+    allocation while the kernels still read or write them."""
+    import contextlib
+    import torch
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def _transform(name, call, x, wavelet, levels, norm, scheme, out, workspace, arithmetic,
-               tile_rows, lds_buffers=0, tile_order="auto", fuse_tail=0):
-    """Allocate out / workspace as needed and run call(opt, ws, ws_bytes) -> status,
-    a closure over the C entry point with the tensors' pointers."""
+               tile_rows, lds_buffers=0, tile_order="auto", fuse_tail=0, stream=None):
+    """Allocate out / workspace as needed (on `stream`'s pool) and run
+    call(opt, ws, ws_bytes) -> status, a closure over the C entry point with
+    the tensors' pointers."""
     import torch
     _check_image(x)
     h, w = x.shape
-    if out is None:
-        out = torch.empty((h, w), dtype=torch.float32, device=x.device)
-    _check_image(out)
     opt = make_options(norm, scheme, arithmetic, tile_rows, lds_buffers, tile_order, fuse_tail)
-    ws, nws = _workspace(wavelet, levels, w, h, opt, x.device, workspace)
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty((h, w), dtype=torch.float32, device=x.device)
+        _check_image(out)
+        ws, nws = _workspace(wavelet, levels, w, h, opt, x.device, workspace)
     st = call(out, opt, ws.data_ptr() if ws is not None else None, nws)
     if st != OK:
         raise Dwt2Error(st, name)
@@ -371,7 +383,7 @@ def forward(img, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=N
                             img.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                             nws, _stream_handle(stream))
     return _transform("dwt2_forward", call, img, wavelet, levels, norm, scheme, out, workspace,
-                      arithmetic, tile_rows, lds_buffers, tile_order, fuse_tail)
+                      arithmetic, tile_rows, lds_buffers, tile_order, fuse_tail, stream)
 
 
 def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=None,
@@ -383,7 +395,7 @@ def inverse(coef, wavelet="cdf53", levels=1, norm="unit_dc", scheme="auto", out=
                             coef.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                             nws, _stream_handle(stream))
     return _transform("dwt2_inverse", call, coef, wavelet, levels, norm, scheme, out, workspace,
-                      arithmetic, tile_rows, lds_buffers, tile_order, fuse_tail)
+                      arithmetic, tile_rows, lds_buffers, tile_order, fuse_tail, stream)
 
 
 def autotune(x, wavelet="cdf53", levels=1, inverse=False, norm="unit_dc", repeats=20, out=None,
@@ -397,7 +409,7 @@ def autotune(x, wavelet="cdf53", levels=1, inverse=False, norm="unit_dc", repeat
                              x.stride(0), y.data_ptr(), y.stride(0), EXT_WHOLE_SYMMETRIC, opt, ws,
                              nws, repeats, _stream_handle(stream))
     return _transform("dwt2_autotune", call, x, wavelet, levels, norm, "auto", out, workspace,
-                      "auto", 0)
+                      "auto", 0, stream=stream)
 
 
 def tile_rows(wavelet, width, height, inverse=False, norm="unit_dc", arithmetic="auto",
@@ -493,11 +505,16 @@ class Batch:
         self.workspace_bytes = workspace.numel() * workspace.element_size()
 
     def __call__(self, stream=None):
+        import torch
         fn = dwt2_inverse_batch if self.inverse else dwt2_forward_batch
         st = fn(self.images, self.count, EXT_WHOLE_SYMMETRIC, self.opt,
                 self.workspace.data_ptr(), self.workspace_bytes, _stream_handle(stream))
         if st != OK:
             raise Dwt2Error(st, fn.__name__)
+        if stream is not None and stream != torch.cuda.current_stream(self.workspace.device):
+            # the workspace came from another stream's pool: keep its block
+            # from reuse until this stream's work has passed it
+            self.workspace.record_stream(stream)
         return self.outputs
 
 
@@ -506,33 +523,40 @@ def forward_batch(images, wavelets, levels, norm="unit_dc", arithmetic="auto", o
     """Forward DWT of a list of (H, W) float32 device tensors in one batched
     call; returns their Mallat layouts."""
     import torch
-    if outs is None:
-        outs = [torch.empty_like(x) for x in images]
-    return Batch(images, outs, wavelets, levels, norm, arithmetic)(stream)
+    with _on_stream(stream):
+        if outs is None:
+            outs = [torch.empty_like(x) for x in images]
+        batch = Batch(images, outs, wavelets, levels, norm, arithmetic)
+    return batch(stream)
 
 
 def inverse_batch(coefs, wavelets, levels, norm="unit_dc", arithmetic="auto", outs=None,
                   stream=None):
     """Inverse DWT of a list of Mallat-layout device tensors in one batched call."""
     import torch
-    if outs is None:
-        outs = [torch.empty_like(x) for x in coefs]
-    return Batch(coefs, outs, wavelets, levels, norm, arithmetic, inverse=True)(stream)
+    with _on_stream(stream):
+        if outs is None:
+            outs = [torch.empty_like(x) for x in coefs]
+        batch = Batch(coefs, outs, wavelets, levels, norm, arithmetic, inverse=True)
+    return batch(stream)
 
 
 class Server:
     """Serving loop over an arena of `arena_bytes` device bytes (allocated here
     with torch).  Requests are (src, dst) device tensors; the server keeps a
-    reference to both until the request is waited for."""
+    reference to both until the request is waited for.  max_footprint_mib
+    caps the device memory (inputs, outputs and LL buffers) of the requests
+    in flight (0: no cap beyond the arena)."""
 
     def __init__(self, arena_bytes, norm="unit_dc", arithmetic="auto", max_batch=0,
-                 max_inflight=0, stream=None, device=None):
+                 max_inflight=0, stream=None, device=None, max_footprint_mib=0):
         import torch
         device = device if device is not None else torch.device("cuda")
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         cfg = ServerConfig()
         cfg.max_batch, cfg.max_inflight = max_batch, max_inflight
+        cfg.max_footprint_mib = int(max_footprint_mib)
         st, self.handle = dwt2_server_create(make_options(norm, "auto", arithmetic), cfg,
                                              self.arena.data_ptr(), int(arena_bytes),
                                              self.stream.cuda_stream)

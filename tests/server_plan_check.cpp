@@ -99,12 +99,50 @@ static size_t table(int count, int lmax) { return 256 * (size_t)count + 256 * (s
 
 static Item req(uintptr_t src, uintptr_t dst, size_t bytes, int inverse, int levels, size_t ll)
 {
-    return Item{src, src + bytes, dst, dst + bytes, inverse, levels, ll};
+    Item it{src, src + bytes, dst, dst + bytes, inverse, levels, ll, 0};
+    it.footprint = footprint_of(it);
+    return it;
 }
 
-static size_t plan(const std::vector<Item> &q, int max_batch, const Arena &a, Group g[2])
+static size_t plan(const std::vector<Item> &q, int max_batch, const Arena &a, Group g[2],
+                   size_t budget = SIZE_MAX, size_t *fp_out = nullptr)
 {
-    return next_batch([&](size_t i) { return q[i]; }, q.size(), max_batch, a, table, g);
+    size_t fp = 0;
+    const size_t n = next_batch([&](size_t i) { return q[i]; }, q.size(), max_batch, a, budget, table, g, &fp);
+    if (fp_out) *fp_out = fp;
+    return n;
+}
+
+// The footprint budget against a brute-force model: the batch is the longest
+// prefix (within max_batch, no range conflicts here) whose footprints sum to
+// at most the budget, and the reported footprint is that sum.
+static void footprints()
+{
+    Arena big(1 << 30);
+    Group g[2];
+    std::vector<Item> q;
+    for (int i = 0; i < 8; i++) q.push_back(req(0x100000 * (2 * i + 1), 0x100000 * (2 * i + 2), 1000, i % 2, 2, 100));
+    CHECK(q[0].footprint == 2100);  // input + output + LL buffers
+    size_t fp = 0;
+    CHECK(plan(q, 256, big, g, SIZE_MAX, &fp) == 8 && fp == 8 * 2100);
+    CHECK(plan(q, 256, big, g, 2099, &fp) == 0 && fp == 0);      // the head alone is over
+    CHECK(plan(q, 256, big, g, 2100, &fp) == 1 && fp == 2100);
+    CHECK(plan(q, 256, big, g, 3 * 2100 + 2099, &fp) == 3 && fp == 3 * 2100);
+    std::mt19937 rng(13);
+    for (int round = 0; round < 300; round++) {
+        std::vector<Item> r;
+        const int n = 1 + rng() % 12;
+        for (int i = 0; i < n; i++)
+            r.push_back(req(0x1000000 * (2 * i + 1), 0x1000000 * (2 * i + 2), 1 + rng() % 5000,
+                            rng() % 2, 1 + rng() % 6, rng() % 3000));
+        const size_t budget = rng() % 40000;
+        const int max_batch = 1 + rng() % 16;
+        size_t want = 0, acc = 0;
+        while (want < r.size() && (int)want < max_batch && acc + r[want].footprint <= budget)
+            acc += r[want++].footprint;
+        CHECK(plan(r, max_batch, big, g, budget, &fp) == want && fp == acc);
+        CHECK(g[0].count + g[1].count == (int)want);
+    }
 }
 
 static void batches()
@@ -146,6 +184,7 @@ int main()
     range_sets();
     arenas();
     batches();
+    footprints();
     printf("ok %d\n", checks);
     return 0;
 }

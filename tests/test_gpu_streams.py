@@ -102,3 +102,34 @@ def test_host_threads_share_the_library():
     assert not errors, errors
     for i in range(len(jobs)):
         assert torch.equal(got[i], want[i]), f"job {i}"
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_stream_argument_keeps_buffers_until_its_work_ran(batched):
+    """forward(..., stream=side) allocates its output and workspace for the
+    side stream: a tensor of the same size allocated and filled on the
+    current stream right after the call, while the side stream is still busy,
+    must not land on the workspace the queued kernels read."""
+    import oracle
+    h, w, lev = 1200, 1500, 3
+    x = image(630, h, w)
+    st, nbytes = dwt2.dwt2_workspace_bytes("cdf97", lev, w, h)
+    assert st == dwt2.OK and nbytes > 0
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(20_000_000)  # hold the side stream (bounded spin)
+    if batched:
+        y = dwt2.forward_batch([x], ["cdf97"], [lev], stream=side)[0]
+    else:
+        y = dwt2.forward(x, "cdf97", lev, stream=side)
+    junk = [torch.full((nbytes // 4 + 1,), float("nan"), device=dev()) for _ in range(4)]
+    junk += [torch.full((h, w), float("nan"), device=dev()) for _ in range(2)]
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    ref = oracle.forward(x.cpu().numpy().astype(np.float64), "cdf97", lev)
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref).max() <= 1e-3
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-6
+    del junk

@@ -19,8 +19,26 @@ WAVELETS = ["cdf53", "cdf97", "dd137"]
 # (width, height, levels, pitch): the tail from level 0 (both sides <= 128),
 # from a deeper level, tall and wide images, and every level down to 2 x 2.
 CASES = [(128, 128, 3, None), (100, 60, 4, None), (37, 22, 3, None), (300, 500, 6, None),
-         (1030, 770, 7, 1040), (64, 3000, 8, None), (3000, 70, 7, None), (129, 128, 5, None),
+         (1030, 770, 7, 1040), (40, 1000, 5, None), (3000, 70, 7, None), (129, 128, 5, None),
          (6, 5, 2, None)]
+
+
+def tail_start(w, h, lev):
+    """First level the library fuses into the tail (lev when none): the first
+    level whose input has both sides <= 128, if at least two levels remain."""
+    for k in range(lev - 1):
+        if w <= 128 and h <= 128:
+            return k
+        w, h = (w + 1) // 2, (h + 1) // 2
+    return lev
+
+
+def test_every_case_reaches_the_tail():
+    for (w, h, lev, _) in CASES:
+        lev = min(lev, max_levels(w, h, 30))
+        assert tail_start(w, h, lev) <= lev - 2, (w, h, lev)
+    assert tail_start(40, 1000, 5) == 3  # tall: level 3's input is 5 x 125
+    assert tail_start(64, 3000, 6) == 6  # level 4 (4 x 188) is too tall, level 5 is the last
 
 
 def placed(a, h, w, pitch, offset):

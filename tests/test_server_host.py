@@ -37,12 +37,13 @@ def test_create_argument_errors():
     o = dwt2.make_options()
     o.arithmetic = 3
     assert create(opt=o) == dwt2.E_UNSUPPORTED
-    for field, val in [("max_batch", -1), ("max_batch", dwt2.BATCH_MAX + 1), ("max_inflight", -1)]:
+    for field, val in [("max_batch", -1), ("max_batch", dwt2.BATCH_MAX + 1), ("max_inflight", -1),
+                       ("max_footprint_mib", -1)]:
         c = dwt2.ServerConfig()
         setattr(c, field, val)
         assert create(cfg=c) == dwt2.E_ARG, field
     c = dwt2.ServerConfig()
-    c.reserved[5] = 2
+    c.reserved[4] = 2
     assert create(cfg=c) == dwt2.E_ARG
     assert create(arena=None) == dwt2.E_WORKSPACE
     assert create(nbytes=255) == dwt2.E_WORKSPACE
