@@ -17,13 +17,20 @@ launches), then W warm-up steps, then K timed steps.  Prints ONE JSON line:
                Monolithic* and Monolithic (2 barriers per pair), separable
                Sweldens (4), Iwahashi, Iwahashi*, Explosive, Explosive* (3) and
                Polyphase* (1), plus the row-column separable two-pass kernels
+  transform_only  the paper's transform-only mode (no image input or output)
+               per scheme at 8192^2: 5/3 and 9/7 in every scheme, DD 13/7 in
+               the fused kernel
+  c1_512       the 512^2 5/3 one-level workload, row-column and fused
+               (cache-resident, launch-bound)
   pyramid      per-level and five-level times of the 16384^2 9/7 pyramid
+  pyramid_cdf53  the same for the 16384^2 5/3 pyramid
   batch        512 uneven images: batched call, HIP-graph replay, and one
                call per image (images/s, p99, fraction of 8 TB/s)
   serve        the serving loop under a Poisson request stream at 0.8 x its
                saturated rate: images/s, p50 / p99 latency
   cpu_baseline the FP64 CPU oracle on the host cores, forward + inverse of the
-               same image
+               same image (all cores), and on one thread (a crop of it)
+GPU times are medians, with the minimum beside them where a table has one.
 """
 from __future__ import annotations
 
@@ -256,10 +263,16 @@ def main():
         out["schemes"] = scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, args.scheme_reps)
     if not args.no_tiles:
         out["tiles"] = tile_table(dwt2, torch, xs[0], ys[0], zs[0], args.scheme_reps)
+    if not args.no_schemes:
+        out["transform_only"] = transform_only_table(dwt2, torch, dev)
+        out["c1_512"] = c1_table(dwt2, torch, workloads, dev)
     if not args.no_pyramid:
         del xs, ys, zs
         torch.cuda.empty_cache()
         out["pyramid"] = pyramid_table(dwt2, torch, workloads, args.scheme_reps)
+        torch.cuda.empty_cache()
+        out["pyramid_cdf53"] = pyramid_table(dwt2, torch, workloads, args.scheme_reps,
+                                             name="cdf53_16384_l5")
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batch"] = batch_table(dwt2, torch, workloads, args.scheme_reps)
@@ -327,13 +340,84 @@ def scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, reps):
         for direction in ("forward", "inverse"):
             f = dwt2.forward if direction == "forward" else dwt2.inverse
             src, dst = (xs[0], ys[0]) if direction == "forward" else (ys[0], zs[0])
-            us = _graph_us(torch, lambda: f(src, wav_, lev, scheme=scheme, out=dst, workspace=ws,
-                                            arithmetic=arith, lds_buffers=nb), reps=reps)
+            us, us_min = _graph_stats(torch, lambda: f(src, wav_, lev, scheme=scheme, out=dst, workspace=ws,
+                                                       arithmetic=arith, lds_buffers=nb), reps=reps)
             gbs = BYTES_PER_PX * npx / (us * 1e-6) / 1e9
-            res[direction] = {"us": round(us, 2), "Gpixel_s": round(npx / (us * 1e-6) / 1e9, 1),
+            res[direction] = {"us": round(us, 2), "min_us": round(us_min, 2),
+                              "Gpixel_s": round(npx / (us * 1e-6) / 1e9, 1),
                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
         table[name] = res
     return table
+
+
+TRANSFORM_ONLY_SCHEMES = ("monolithic*", "monolithic*-tile", "monolithic", "explosive*", "explosive",
+                          "iwahashi*", "sweldens", "iwahashi", "polyphase*")
+
+
+def transform_only_table(dwt2, torch, dev, n=8192):
+    """The paper's transform-only mode (Sec. 6, Experiments 1 and 2): one
+    level of an n x n image per scheme with no image input or output
+    (dwt2_transform_only), device time per launch from a HIP graph (median
+    and min), for the degree-1 wavelets (5/3 and 9/7) and, in the fused
+    kernel, the degree-3 DD 13/7."""
+    lib = dwt2.library()
+    sink = torch.zeros(1, dtype=torch.float32, device=dev)
+    out = {"size": [n, n], "unit": "us per launch / Gpixel/s"}
+    for wav in ("cdf53", "cdf97", "dd137"):
+        row = {}
+        for scheme in TRANSFORM_ONLY_SCHEMES if wav != "dd137" else ("monolithic*",):
+            opt = dwt2.make_options(scheme=scheme)
+            res = {}
+            for inverse in (0, 1):
+                def call():
+                    st = lib.dwt2_transform_only(inverse, dwt2.WAVELETS[wav], n, n, ctypes.byref(opt),
+                                                 sink.data_ptr(), torch.cuda.current_stream().cuda_stream)
+                    if st != dwt2.OK:
+                        raise dwt2.Dwt2Error(st, "dwt2_transform_only")
+                med, mn = _graph_stats(torch, call)
+                d = "inverse" if inverse else "forward"
+                res[d + "_us"] = round(med, 2)
+                res[d + "_min_us"] = round(mn, 2)
+                res[d + "_Gpixel_s"] = round(n * n / med / 1e3, 1)
+            row[scheme] = res
+        if wav != "dd137":
+            row["monolithic*_vs_sweldens"] = round(row["sweldens"]["forward_us"] /
+                                                   row["monolithic*"]["forward_us"], 3)
+            row["monolithic*-tile_vs_sweldens"] = round(row["sweldens"]["forward_us"] /
+                                                        row["monolithic*-tile"]["forward_us"], 3)
+        out[wav] = row
+    torch.cuda.synchronize()
+    assert float(sink[0]) == 0.0  # never written
+    return out
+
+
+def c1_table(dwt2, torch, workloads, dev):
+    """The 512^2 CDF 5/3 one-level workload (uniform 0-255 integers, seed 0),
+    plain separable row-column lifting and the fused kernel: device time per
+    call from a HIP graph (median and min).  2 MiB in and out stay in the
+    caches, so the launch latency bounds it and the HBM fraction does not
+    apply."""
+    name = "cdf53_512_l1"
+    spec = workloads.WORKLOADS[name]
+    W, H = spec["width"], spec["height"]
+    x = torch.from_numpy(workloads.workload_image(name)).to(dev)
+    out = {"workload": f"{name} ({W}x{H}, cdf53, 1 level, uniform 0-255 integers, seed 0)",
+           "bound": "launch latency (cache-resident)"}
+    for scheme in ("rowcol", "monolithic*"):
+        st, nbytes = dwt2.dwt2_workspace_bytes("cdf53", 1, W, H, dwt2.make_options(scheme=scheme))
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        y, z = torch.empty_like(x), torch.empty_like(x)
+        tf, tf_min = _graph_stats(torch, lambda: dwt2.forward(x, "cdf53", 1, scheme=scheme, out=y,
+                                                              workspace=ws))
+        ti, ti_min = _graph_stats(torch, lambda: dwt2.inverse(y, "cdf53", 1, scheme=scheme, out=z,
+                                                              workspace=ws))
+        torch.cuda.synchronize()
+        out[scheme] = {"forward_us": round(tf, 2), "forward_min_us": round(tf_min, 2),
+                       "inverse_us": round(ti, 2), "inverse_min_us": round(ti_min, 2),
+                       "forward_Gpixel_s": round(W * H / tf / 1e3, 1),
+                       "inverse_Gpixel_s": round(W * H / ti / 1e3, 1),
+                       "round_trip_max_abs": float((z - x).abs().max())}
+    return out
 
 
 def _median_us(torch, fn, reps):
@@ -351,11 +435,16 @@ def _median_us(torch, fn, reps):
 
 
 def _graph_us(torch, fn, n=20, reps=5, warm_s=0.03):
+    """Median device time per call of fn (see _graph_stats)."""
+    return _graph_stats(torch, fn, n, reps, warm_s)[0]
+
+
+def _graph_stats(torch, fn, n=20, reps=5, warm_s=0.03):
     """Device time per call of fn, from a HIP graph of n back-to-back calls
     (host launch overhead excluded; what remains is the kernels and the gaps
-    between graph nodes).  Median over reps replays, after untimed replays
-    for at least warm_s seconds: kernels launched right after the idle gap
-    of a graph capture were measured ~3 % slower."""
+    between graph nodes): (median, min) over reps replays, after untimed
+    replays for at least warm_s seconds (kernels launched right after the idle
+    gap of a graph capture were measured ~3 % slower)."""
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -381,16 +470,15 @@ def _graph_us(torch, fn, n=20, reps=5, warm_s=0.03):
         e1.record(stream)
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1) * 1e3 / n)
-    return statistics.median(ts)
+    return statistics.median(ts), min(ts)
 
 
-def pyramid_table(dwt2, torch, workloads, reps):
-    """Per-level forward and inverse of the fused kernel on the 16384^2 CDF 9/7
+def pyramid_table(dwt2, torch, workloads, reps, name="cdf97_16384_l5"):
+    """Per-level forward and inverse of the fused kernel on a 16384^2
     five-level workload: each level's input size timed as a one-level call on
     the LL band the previous level produced (device time per call from a HIP
-    graph of back-to-back calls) in the tile order the rule picks and in the
-    other one, plus the whole five-level call."""
-    name = "cdf97_16384_l5"
+    graph of back-to-back calls: median and min) in the tile order the rule
+    picks and in the other one, plus the whole five-level call."""
     spec = workloads.WORKLOADS[name]
     W, H, wav, lev = spec["width"], spec["height"], spec["wavelet"], spec["levels"]
     dev = torch.device("cuda:0")
@@ -404,8 +492,8 @@ def pyramid_table(dwt2, torch, workloads, reps):
         src = cur.contiguous()
         dst = torch.empty_like(src)
         back = torch.empty_like(src)
-        tf = _graph_us(torch, lambda: dwt2.forward(src, wav, 1, out=dst))
-        ti = _graph_us(torch, lambda: dwt2.inverse(dst, wav, 1, out=back))
+        tf, tf_min = _graph_stats(torch, lambda: dwt2.forward(src, wav, 1, out=dst))
+        ti, ti_min = _graph_stats(torch, lambda: dwt2.inverse(dst, wav, 1, out=back))
         order = [dwt2.tile_order(wav, w, h), dwt2.tile_order(wav, w, h, inverse=True)]
         other = ["bands" if o == "runs" else "runs" for o in order]
         of = _graph_us(torch, lambda: dwt2.forward(src, wav, 1, out=dst, tile_order=other[0]))
@@ -413,6 +501,7 @@ def pyramid_table(dwt2, torch, workloads, reps):
         npx = w * h
         levels.append({"level": k + 1, "width": w, "height": h, "tile_order": order,
                        "forward_us": round(tf, 2), "inverse_us": round(ti, 2),
+                       "forward_min_us": round(tf_min, 2), "inverse_min_us": round(ti_min, 2),
                        "other_order_us": [round(of, 2), round(oi, 2)],
                        "forward_Gpixel_s": round(npx / tf / 1e3, 1),
                        "inverse_Gpixel_s": round(npx / ti / 1e3, 1),
@@ -425,12 +514,15 @@ def pyramid_table(dwt2, torch, workloads, reps):
     # Device time per five-level call, from a HIP graph as the levels above
     # (a single eager call also counts the binding's host work before its
     # first launch, tens of microseconds).
-    tf = _graph_us(torch, lambda: dwt2.forward(x, wav, lev, out=y, workspace=ws), n=10)
-    ti = _graph_us(torch, lambda: dwt2.inverse(y, wav, lev, out=z, workspace=ws), n=10)
+    tf, tf_min = _graph_stats(torch, lambda: dwt2.forward(x, wav, lev, out=y, workspace=ws), n=10)
+    ti, ti_min = _graph_stats(torch, lambda: dwt2.inverse(y, wav, lev, out=z, workspace=ws), n=10)
     te = _median_us(torch, lambda i: dwt2.forward(x, wav, lev, out=y, workspace=ws), reps)
     total_px = sum(l["width"] * l["height"] for l in levels)
     return {"workload": f"{name} ({W}x{H}, {wav}, {lev} levels, fused kernel)", "levels": levels,
             "five_level_forward_us": round(tf, 1), "five_level_inverse_us": round(ti, 1),
+            "five_level_forward_min_us": round(tf_min, 1), "five_level_inverse_min_us": round(ti_min, 1),
+            "sum_of_levels_forward_us": round(sum(l["forward_us"] for l in levels), 1),
+            "sum_of_levels_inverse_us": round(sum(l["inverse_us"] for l in levels), 1),
             "five_level_forward_eager_us": round(te, 1),
             "five_level_forward_Gpixel_s": round(total_px / tf / 1e3, 1),
             "five_level_inverse_Gpixel_s": round(total_px / ti / 1e3, 1)}
@@ -474,8 +566,8 @@ def batch_table(dwt2, torch, workloads, reps):
 
     def row(times):
         med = statistics.median(times)
-        return {"median_us": round(med, 1), "p99_us": round(times[min(len(times) - 1,
-                                                                       int(0.99 * len(times)))], 1),
+        return {"median_us": round(med, 1), "min_us": round(times[0], 1),
+                "p99_us": round(times[min(len(times) - 1, int(0.99 * len(times)))], 1),
                 "images_per_s": round(n / med * 1e6, 1),
                 "Gpixel_s": round(px0 / med / 1e3, 1),
                 "hbm_frac": round(BYTES_PER_PX * px_all / med / 1e3 / HBM_PEAK_GBS, 4)}
@@ -632,28 +724,59 @@ def copy_bandwidth(torch, dev):
     return round(2 * 4 * n / t / 1e9, 1)
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, x, wav, lev, budget_s):
+    """(Gpixel/s, reps, seconds) of forward + inverse of x: median of per-rep
+    rates over about budget_s seconds after one warm-up."""
+    y = oracle.forward(x, wav, lev)
+    oracle.inverse(y, wav, lev)
+    rates, t_all = [], time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        y = oracle.forward(x, wav, lev)
+        oracle.inverse(y, wav, lev)
+        rates.append(2 * x.size / (time.perf_counter() - t0) / 1e9)
+        if time.perf_counter() - t_all >= budget_s and len(rates) >= 3:
+            break
+    return statistics.median(rates), len(rates), time.perf_counter() - t_all
+
+
 def cpu_baseline(img, wav, lev, budget_s):
+    """The FP64 C oracle on the host: all cores (OpenMP) on the full image,
+    and one thread on a 2048 x 2048 crop of it (the rate per pixel does not
+    depend on the size at these sizes; the crop keeps the run short)."""
     import numpy as np
 
     import oracle
 
     x = img.astype(np.float64)
     threads = oracle.num_threads()
-    t0 = time.perf_counter()
-    y = oracle.forward(x, wav, lev)
-    oracle.inverse(y, wav, lev)
-    one = time.perf_counter() - t0
-    reps = max(1, int(budget_s / max(one, 1e-3)) - 1)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        y = oracle.forward(x, wav, lev)
-        oracle.inverse(y, wav, lev)
-    t = time.perf_counter() - t0
-    npx = x.size
-    return {"value": round(2 * npx * reps / t / 1e9, 4), "unit": "Gpixel/s", "cores": threads,
+    affinity = len(os.sched_getaffinity(0))
+    rate, reps, t = _oracle_rate(oracle, x, wav, lev, 0.7 * budget_s)
+    crop = np.ascontiguousarray(x[:2048, :2048])
+    oracle.set_num_threads(1)
+    try:
+        rate1, reps1, t1 = _oracle_rate(oracle, crop, wav, lev, 0.3 * budget_s)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": round(rate, 4), "unit": "Gpixel/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"full {x.shape[1]}x{x.shape[0]} image, forward+inverse, {reps} reps "
-                      f"after 1 warm-up ({t:.1f} s), FP64 C with OpenMP"}
+            "sample": f"full {x.shape[1]}x{x.shape[0]} image, forward+inverse, median of {reps} reps "
+                      f"after 1 warm-up ({t:.1f} s), FP64 C with OpenMP on {threads} threads",
+            "single_thread": {"value": round(rate1, 5), "unit": "Gpixel/s", "cores": 1,
+                              "sample": f"2048x2048 crop, forward+inverse, median of {reps1} reps "
+                                        f"after 1 warm-up ({t1:.1f} s)"},
+            "cpu_model": _cpu_model(), "affinity_cpus": affinity}
 
 
 if __name__ == "__main__":

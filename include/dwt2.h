@@ -257,6 +257,25 @@ int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int height,
                  size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Transform-only measurement (the paper's Sec. 6 mode that leaves out the
+ * input and output of data, used by its Experiments 1 and 2).  Enqueues one
+ * level of the forward (inverse == 0) or inverse transform of a width x height
+ * image with the kernel `opt` selects (scheme, and for MONOLITHIC_STAR the
+ * tile height, buffering and order, as dwt2_forward would pick them), except
+ * that no image memory is read or written: every tile synthesises its samples
+ * in registers from its coordinates, lifts them with all of the scheme's
+ * arithmetic, wavefront shifts, LDS traffic and barriers, and keeps the
+ * results.  Each work-group compares a checksum of its results with a NaN
+ * pattern that finite data never produce and would store it to sink[0] on a
+ * match, so the compiler keeps all the work and nothing is stored.  For
+ * timing only; the result is not a transform of anything.  sink: a device
+ * pointer to 4 writable bytes, 4-byte aligned.  FP32 lifting only; ROWCOL and
+ * fuse_tail -> DWT2_E_UNSUPPORTED; sizes as dwt2_forward with levels = 1.
+ */
+int dwt2_transform_only(int inverse, dwt2_wavelet wavelet, int width, int height,
+                        const dwt2_options *opt, float *sink, hipStream_t stream);
+
+/*
  * Batched transforms
  * ------------------
  * Many independent images, each with its own wavelet, level count and size,
@@ -304,6 +323,23 @@ int dwt2_forward_batch(const dwt2_image *images, int count, dwt2_ext ext,
 int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext ext,
                        const dwt2_options *opt, void *workspace, size_t workspace_bytes,
                        hipStream_t stream);
+
+/*
+ * Tile heights of a batched call.  Each image's level runs at the height
+ * dwt2_autotune recorded for its wavelet, direction and level size (FP32
+ * lifting), else at its wavelet's tallest built height; when the level
+ * launch would then have fewer than 1024 work-groups (four per compute
+ * unit), the untuned images step down to shorter heights together until it
+ * has, as far as the built heights go (the rule of dwt2_options.tile_rows,
+ * applied to the launch instead of one image).  FP64 lifting runs at its one
+ * height.  Heights change speed only, never the result.  Writes
+ * rows[0..count) for level `level` (0-based) of the forward (inverse == 0) or
+ * inverse call with these arguments: an image's height, or 0 when it has no
+ * such level.  Statuses as dwt2_batch_workspace_bytes; level < 0 or a null
+ * rows with count > 0 -> DWT2_E_ARG.
+ */
+int dwt2_batch_tile_rows(int inverse, const dwt2_image *images, int count,
+                         const dwt2_options *opt, int level, int *rows);
 
 /*
  * Serving loop (continuous batching)
@@ -407,20 +443,27 @@ int dwt2_server_destroy(dwt2_server *server);
  *
  * dwt2_autotune runs the transform that dwt2_forward (inverse == 0) or
  * dwt2_inverse (inverse != 0) runs with the same arguments and leaves the same
- * result in dst.  Along the way it runs each level `repeats` times at every
- * built FP32 height in both tile orders (three passes, each after one untimed
- * launch of the candidate), times the runs with HIP
- * events on `stream`, and records the fastest height and order for (wavelet,
- * direction, level width, level height) in a table shared by the process
- * (entries are replaced; the table holds at most 4096 entries, further sizes
- * are not recorded).  Later FP32 calls with tile_rows == 0 (tile_order ==
- * AUTO) use the recorded height (order) of a level of that exact size.
+ * result in dst.  It first waits for the work already on `stream`, then runs
+ * on a stream of its own: for each level, every built FP32 height in both
+ * tile orders is captured as a HIP graph of `repeats` back-to-back launches,
+ * and the graphs are replayed in five interleaved passes (each starting at
+ * another candidate, after one untimed replay of each) timed with HIP events.
+ * A candidate's time is the median of its passes.  The height and order the
+ * rules above pick are kept unless another candidate is faster by more than
+ * the spread (slowest minus fastest pass) of either, and the choice is
+ * recorded for (wavelet, direction, level width, level height) in a table
+ * shared by the process (entries are replaced; the table holds at most 4096
+ * entries, further sizes are not recorded).  Later FP32 calls with
+ * tile_rows == 0 (tile_order == AUTO) use the recorded height (order) of a
+ * level of that exact size, and batched calls the recorded height.  The call creates and
+ * destroys a stream, two events and the graphs; it allocates no device
+ * memory of its own.
  * Argument rules are those of dwt2_forward; the scheme must be AUTO or
  * MONOLITHIC_STAR, the arithmetic AUTO or FP32, tile_rows, lds_buffers and
  * tile_order 0, else DWT2_E_UNSUPPORTED; repeats must be in [1, 1000], else
- * DWT2_E_ARG.  The call blocks until its work on `stream` is done and must
- * not be captured in a graph.  The table is locked internally: any thread may
- * call any function.
+ * DWT2_E_ARG.  The call blocks until its work is done and must not be
+ * called while `stream` is being captured.  The table is locked internally:
+ * any thread may call any function.
  */
 int dwt2_autotune(int inverse, dwt2_wavelet wavelet, int levels, int width, int height,
                   const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
@@ -474,6 +517,16 @@ const char *dwt2_status_string(int status);
 
 /* hipError_t of the last DWT2_E_HIP returned on the calling thread (0 if none). */
 int dwt2_last_hip_error(void);
+
+/*
+ * Fault injection for tests of error handling: the next `count` kernel
+ * launches the calling thread makes through the library return
+ * hipErrorInvalidConfiguration without launching anything (so the call that
+ * makes one returns DWT2_E_HIP, and dwt2_last_hip_error() that code); 0
+ * turns it off.  Launches made by a server's own threads are not affected.
+ * count < 0 -> DWT2_E_ARG.
+ */
+int dwt2_debug_fail_launches(int count);
 
 /* DWT2_VERSION of the loaded library. */
 int dwt2_version(void);

@@ -25,6 +25,7 @@
 namespace {
 
 thread_local int g_last_hip_error = 0;
+thread_local int g_fail_launches = 0;  // dwt2_debug_fail_launches
 
 constexpr int kMaxLevels = 31;
 // 2^38 pixels (1 TiB of FP32) bounds every grid well inside int range.
@@ -272,9 +273,11 @@ struct Checked {
     Layout lay;
 };
 
+// check_ws = false skips the workspace checks (the caller supplies it later).
 int check_call(dwt2_wavelet wavelet, int levels, int width, int height, const float *src,
                ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch, dwt2_ext ext,
-               const dwt2_options *opt, void *workspace, size_t workspace_bytes, Checked *c)
+               const dwt2_options *opt, void *workspace, size_t workspace_bytes, Checked *c,
+               bool check_ws = true)
 {
     int st = parse(wavelet, ext, opt, &c->cfg);
     if (st != DWT2_OK) return st;
@@ -286,9 +289,10 @@ int check_call(dwt2_wavelet wavelet, int levels, int width, int height, const fl
     if (!span_fits(src_pitch, width, height) || !span_fits(dst_pitch, width, height)) return DWT2_E_ARG;
     if (((uintptr_t)src & 3) || ((uintptr_t)dst & 3)) return DWT2_E_ARG;
     c->lay = layout(c->cfg.scheme, levels, c->ws, c->hs);
+    const size_t ns = span_bytes(src_pitch, width, height), nd = span_bytes(dst_pitch, width, height);
+    if (!check_ws) return overlap(src, ns, dst, nd) ? DWT2_E_ALIAS : DWT2_OK;
     if (c->lay.total > 0 && (!workspace || workspace_bytes < c->lay.total)) return DWT2_E_WORKSPACE;
     if (c->lay.total > 0 && ((uintptr_t)workspace & (kAlign - 1))) return DWT2_E_ARG;
-    const size_t ns = span_bytes(src_pitch, width, height), nd = span_bytes(dst_pitch, width, height);
     if (overlap(src, ns, dst, nd)) return DWT2_E_ALIAS;
     if (c->lay.total > 0 &&
         (overlap(workspace, c->lay.total, src, ns) || overlap(workspace, c->lay.total, dst, nd)))
@@ -377,6 +381,20 @@ int hip_status(hipError_t e)
 }
 
 }  // namespace
+
+bool dwt2::take_launch_failure()
+{
+    if (g_fail_launches <= 0) return false;
+    g_fail_launches--;
+    return true;
+}
+
+DWT2_EXPORT int dwt2_debug_fail_launches(int count)
+{
+    if (count < 0) return DWT2_E_ARG;
+    g_fail_launches = count;
+    return DWT2_OK;
+}
 
 DWT2_EXPORT int dwt2_version(void) { return DWT2_VERSION; }
 
@@ -487,14 +505,43 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
     return DWT2_OK;
 }
 
+DWT2_EXPORT int dwt2_transform_only(int inverse, dwt2_wavelet wavelet, int width, int height,
+                                    const dwt2_options *opt, float *sink, hipStream_t stream)
+{
+    Config c;
+    int st = parse(wavelet, DWT2_EXT_WHOLE_SYMMETRIC, opt, &c);
+    if (st != DWT2_OK) return st;
+    if (c.arithmetic != DWT2_ARITH_FP32 || c.scheme == DWT2_SCHEME_ROWCOL || c.fuse_tail)
+        return DWT2_E_UNSUPPORTED;
+    if (width < 1 || height < 1 || !sink || ((uintptr_t)sink & 3)) return DWT2_E_ARG;
+    if (width < 2 || height < 2 || (long long)width * height > kMaxPixels) return DWT2_E_SIZE;
+    dwt2::NoneArgs a;
+    a.W = width;
+    a.H = height;
+    a.sink = sink;
+    a.key = 0xFFFFFFFFu;  // a NaN pattern: never the sum of finite lifted samples
+    const bool inv = inverse != 0;
+    const hipError_t e =
+        c.scheme == DWT2_SCHEME_MONOLITHIC_STAR
+            ? dwt2::launch_fused_none(inv, c.wavelet, choose_rows(c, inv, width, height), buffers_of(c, inv),
+                                      choose_order(c, inv, width, height), a, stream)
+            : dwt2::launch_tile_none(inv, c.wavelet, c.scheme, a, stream);
+    return hip_status(e);
+}
+
 // ---------------------------------------------------------------------------
 // Batched calls.  Workspace: [image records | tile-start table | each image's
 // LL ping-pong, laid out as for the single-image call], each part 256-aligned.
 
+// Tile-height table: one byte per image and level, rows of `count` bytes
+// padded to a multiple of 4 (the upload copies whole words).
+static size_t rows_stride(int count) { return ((size_t)count + 3) & ~(size_t)3; }
+
 size_t dwt2::batch_table_bytes(int count, int lmax)
 {
     return align_up(sizeof(dwt2::BatchImage) * (size_t)count) +
-           align_up(sizeof(int) * (size_t)lmax * (size_t)(count + 1));
+           align_up(sizeof(int) * (size_t)lmax * (size_t)(count + 1)) +
+           align_up(rows_stride(count) * (size_t)lmax);
 }
 
 namespace {
@@ -522,15 +569,82 @@ bool any_write_overlap(std::vector<Interval> &v)
 struct BatchPlan {
     Config cfg;
     int lmax = 0;
-    size_t rec_off = 0, tab_off = 0, total = 0;
+    size_t rec_off = 0, tab_off = 0, rows_off = 0, total = 0;
     std::vector<dwt2::BatchImage> rec;  // buffers as offsets until bound to a workspace
     std::vector<size_t> buf_off[2];
     std::vector<int> start;             // lmax x (count + 1)
+    std::vector<unsigned char> rows;    // lmax x rows_stride(count): tile height per image
     std::vector<std::pair<size_t, size_t>> spans;  // (src bytes, dst bytes)
 };
 
+// Tile heights of batched level k.  An image level whose size dwt2_autotune
+// recorded takes the recorded height (FP32 lifting).  The others take, per
+// wavelet, the tallest built height, or a shorter one when the launch would
+// otherwise have fewer than kFillTiles work-groups: step s takes the s-th
+// height down from the tallest (the shortest when a wavelet has fewer), and
+// the launch uses the smallest step that reaches kFillTiles (else the
+// largest), as the single-image rule does for one image.  FP64 lifting is
+// built at one height per wavelet.  Fills rows[i] (0 without level k) and
+// returns the launch's tile count.
+long long batch_level_rows(const BatchPlan &p, bool inverse, int k, unsigned char *rows)
+{
+    const int count = (int)p.rec.size();
+    const bool fp64 = p.cfg.arithmetic == DWT2_ARITH_FP64;
+    auto level_wh = [&](const dwt2::BatchImage &r, int *w, int *h) {
+        *w = (int)(((long long)r.W + (1LL << k) - 1) >> k);
+        *h = (int)(((long long)r.H + (1LL << k) - 1) >> k);
+    };
+    auto height_at = [](int wavelet, int step) {
+        int n = 0;
+        while (n < dwt2::kFusedRowsMax && dwt2::kFusedRows[wavelet][n] > 0) n++;
+        return dwt2::kFusedRows[wavelet][std::max(0, n - 1 - step)];
+    };
+    std::vector<int> tuned_rows(count, 0);
+    long long fixed = 0;  // tiles of images whose height does not depend on the step
+    for (int i = 0; i < count; i++) {
+        const dwt2::BatchImage &r = p.rec[i];
+        if (r.levels <= k) continue;
+        int w, h;
+        level_wh(r, &w, &h);
+        Config c = p.cfg;
+        c.wavelet = r.wavelet;
+        TuneVal v;
+        if (fp64) tuned_rows[i] = dwt2::kFusedRowsFp64[r.wavelet];
+        else if (tuned(c, inverse, w, h, &v)) tuned_rows[i] = v.rows;
+        if (tuned_rows[i]) fixed += dwt2::fused_tile_count(r.wavelet, tuned_rows[i], w, h);
+    }
+    constexpr int kSteps = dwt2::kFusedRowsMax;
+    int step = kSteps - 1;
+    for (int st = 0; st < kSteps; st++) {
+        long long total = fixed;
+        for (int i = 0; i < count; i++) {
+            const dwt2::BatchImage &r = p.rec[i];
+            if (r.levels <= k || tuned_rows[i]) continue;
+            int w, h;
+            level_wh(r, &w, &h);
+            total += dwt2::fused_tile_count(r.wavelet, height_at(r.wavelet, st), w, h);
+        }
+        if (total >= kFillTiles) {
+            step = st;
+            break;
+        }
+    }
+    long long total = 0;
+    for (int i = 0; i < count; i++) {
+        const dwt2::BatchImage &r = p.rec[i];
+        rows[i] = 0;
+        if (r.levels <= k) continue;
+        int w, h;
+        level_wh(r, &w, &h);
+        const int rb = tuned_rows[i] ? tuned_rows[i] : height_at(r.wavelet, step);
+        rows[i] = (unsigned char)rb;
+        total += dwt2::fused_tile_count(r.wavelet, rb, w, h);
+    }
+    return total;
+}
+
 int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_options *opt,
-               BatchPlan *p)
+               bool inverse, BatchPlan *p)
 {
     if (count < 0 || count > DWT2_BATCH_MAX || (count > 0 && !images)) return DWT2_E_ARG;
     int st = parse(DWT2_CDF53, ext, opt, &p->cfg);
@@ -574,9 +688,14 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
         r.levels = im.levels;
         p->lmax = std::max(p->lmax, im.levels);
     }
-    // Tile starts per level; every level's total must index with an int.
+    // Tile heights and starts per level; every level's total must index with
+    // an int.
+    const size_t rs = rows_stride(count);
     p->start.assign((size_t)p->lmax * (count + 1), 0);
+    p->rows.assign((size_t)p->lmax * rs, 0);
     for (int k = 0; k < p->lmax; k++) {
+        unsigned char *rows = &p->rows[(size_t)k * rs];
+        if (batch_level_rows(*p, inverse, k, rows) > INT_MAX - 8) return DWT2_E_ARG;
         int *s = &p->start[(size_t)k * (count + 1)];
         long long acc = 0;
         for (int i = 0; i < count; i++) {
@@ -585,14 +704,14 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
             if (r.levels > k) {
                 const int w = (int)(((long long)r.W + (1LL << k) - 1) >> k);
                 const int h = (int)(((long long)r.H + (1LL << k) - 1) >> k);
-                acc += dwt2::fused_tile_count(r.wavelet, dwt2::kBatchRows[r.wavelet], w, h);
+                acc += dwt2::fused_tile_count(r.wavelet, rows[i], w, h);
             }
-            if (acc > INT_MAX - 8) return DWT2_E_ARG;
         }
         s[count] = (int)acc;
     }
     p->rec_off = 0;
     p->tab_off = align_up(sizeof(dwt2::BatchImage) * (size_t)count);
+    p->rows_off = p->tab_off + align_up(sizeof(int) * (size_t)p->lmax * (size_t)(count + 1));
     const size_t img_base = dwt2::batch_table_bytes(count, p->lmax);
     for (int i = 0; i < count; i++) {
         p->buf_off[0][i] += img_base;
@@ -606,7 +725,7 @@ int run_batch(bool inverse, const dwt2_image *images, int count, dwt2_ext ext,
               const dwt2_options *opt, void *workspace, size_t workspace_bytes, hipStream_t stream)
 {
     BatchPlan p;
-    int st = plan_batch(images, count, ext, opt, &p);
+    int st = plan_batch(images, count, ext, opt, inverse, &p);
     if (st != DWT2_OK) return st;
     if (count == 0) return DWT2_OK;
     if (!workspace || workspace_bytes < p.total) return DWT2_E_WORKSPACE;
@@ -631,6 +750,7 @@ int run_batch(bool inverse, const dwt2_image *images, int count, dwt2_ext ext,
                                        sizeof(dwt2::BatchImage) * (size_t)count, stream);
     if (e == hipSuccess)
         e = dwt2::launch_upload(wsb + p.tab_off, p.start.data(), sizeof(int) * p.start.size(), stream);
+    if (e == hipSuccess) e = dwt2::launch_upload(wsb + p.rows_off, p.rows.data(), p.rows.size(), stream);
     if (e != hipSuccess) return hip_status(e);
 
     dwt2::BatchLevel b;
@@ -647,6 +767,7 @@ int run_batch(bool inverse, const dwt2_image *images, int count, dwt2_ext ext,
         const int k = inverse ? p.lmax - 1 - j : j;
         b.level = k;
         b.start = (const int *)(wsb + p.tab_off) + (size_t)k * (count + 1);
+        b.rows = (const unsigned char *)(wsb + p.rows_off) + (size_t)k * rows_stride(count);
         b.ntiles = p.start[(size_t)k * (count + 1) + count];
         b.quantum = norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
         e = inverse ? dwt2::launch_batch_inverse(fp64, has_dd, b, stream)
@@ -663,9 +784,22 @@ DWT2_EXPORT int dwt2_batch_workspace_bytes(const dwt2_image *images, int count,
 {
     if (!bytes) return DWT2_E_ARG;
     BatchPlan p;
-    const int st = plan_batch(images, count, DWT2_EXT_WHOLE_SYMMETRIC, opt, &p);
+    const int st = plan_batch(images, count, DWT2_EXT_WHOLE_SYMMETRIC, opt, false, &p);
     if (st != DWT2_OK) return st;
     *bytes = p.total;
+    return DWT2_OK;
+}
+
+DWT2_EXPORT int dwt2_batch_tile_rows(int inverse, const dwt2_image *images, int count,
+                                     const dwt2_options *opt, int level, int *rows)
+{
+    if (!rows && count > 0) return DWT2_E_ARG;
+    BatchPlan p;
+    const int st = plan_batch(images, count, DWT2_EXT_WHOLE_SYMMETRIC, opt, inverse != 0, &p);
+    if (st != DWT2_OK) return st;
+    if (level < 0) return DWT2_E_ARG;
+    for (int i = 0; i < count; i++)
+        rows[i] = level < p.lmax ? p.rows[(size_t)level * rows_stride(count) + i] : 0;
     return DWT2_OK;
 }
 
@@ -688,34 +822,60 @@ DWT2_EXPORT int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext
 
 namespace {
 
-// Mean time of `repeats` back-to-back launches of one level at `rows` and
-// `order`, in ms, after one untimed launch (the previous candidate's
-// traffic and any first-launch cost stay out of the timing).
-int time_level(bool inverse, const Checked &c, const void *args, int rows, int order, int repeats,
-               hipEvent_t e0, hipEvent_t e1, hipStream_t stream, float *ms)
+// Autotuning.  Every candidate (built height x tile order) of a level is
+// captured once as a HIP graph of `repeats` back-to-back launches on a
+// private stream; the graphs are replayed in kTunePasses interleaved passes
+// (each pass starts at another candidate, after one untimed replay of every
+// candidate), each replay timed with events, so all candidates see the same
+// device state and clocks and no host launch gap enters the times.  A
+// candidate's time is the median of its passes.  The rule's candidate is
+// kept unless another one is faster by more than the spread (max - min over
+// the passes) of either of the two: a difference inside the noise does not
+// override the rule.
+constexpr int kTunePasses = 5;
+
+struct TuneRun {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<hipGraphExec_t> exec;
+    std::vector<hipGraph_t> graph;
+    // Destroys the graphs (after the stream has finished their replays).
+    void release_graphs()
+    {
+        for (hipGraphExec_t g : exec)
+            if (g) (void)hipGraphExecDestroy(g);
+        for (hipGraph_t g : graph)
+            if (g) (void)hipGraphDestroy(g);
+        exec.clear();
+        graph.clear();
+    }
+};
+
+hipError_t capture_level(bool inverse, const Checked &c, const void *args, int rows, int order, int repeats,
+                         hipStream_t s, hipGraph_t *g, hipGraphExec_t *ge)
 {
-    auto run = [&]() {
-        return inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg, inverse), order,
-                                                    *(const dwt2::InvArgs *)args, stream)
-                       : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg, inverse), order,
-                                                    *(const dwt2::FwdArgs *)args, stream);
-    };
-    hipError_t e = run();
-    if (e == hipSuccess) e = hipEventRecord(e0, stream);
-    for (int i = 0; i < repeats && e == hipSuccess; i++) e = run();
-    if (e == hipSuccess) e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
-    if (e != hipSuccess) return hip_status(e);
-    *ms /= (float)repeats;
-    return DWT2_OK;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < repeats && le == hipSuccess; i++)
+        le = inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg, inverse), order,
+                                                  *(const dwt2::InvArgs *)args, s)
+                     : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg, inverse), order,
+                                                  *(const dwt2::FwdArgs *)args, s);
+    e = hipStreamEndCapture(s, g);  // always ends the capture
+    if (le != hipSuccess) return le;
+    if (e != hipSuccess) return e;
+    return hipGraphInstantiate(ge, *g, nullptr, nullptr, 0);
 }
 
 int tune(bool inverse, const Checked &c, const float *src, ptrdiff_t src_pitch, float *dst,
-         ptrdiff_t dst_pitch, void *workspace, int repeats, hipStream_t stream, hipEvent_t e0,
-         hipEvent_t e1)
+         ptrdiff_t dst_pitch, void *workspace, int repeats, TuneRun &run)
 {
     const int *cand = dwt2::kFusedRows[c.cfg.wavelet];
+    int nrows = 0;
+    while (nrows < dwt2::kFusedRowsMax && cand[nrows] > 0) nrows++;
+    constexpr int kOrders[2] = {DWT2_ORDER_RUNS, DWT2_ORDER_BANDS};
+    const int ncand = 2 * nrows;
     for (int j = 0; j < c.levels; j++) {
         const int k = inverse ? c.levels - 1 - j : j;
         dwt2::FwdArgs fa;
@@ -728,33 +888,55 @@ int tune(bool inverse, const Checked &c, const float *src, ptrdiff_t src_pitch, 
             fa = forward_level(c, k, src, src_pitch, dst, dst_pitch, workspace);
             args = &fa;
         }
-        // Three passes over every (height, order), each pass starting at
-        // another candidate; each candidate keeps its fastest pass.  Every
-        // run writes the same level output, so the next level reads the
-        // result.
-        constexpr int kOrders[2] = {DWT2_ORDER_RUNS, DWT2_ORDER_BANDS};
-        int ncand = 0;
-        while (ncand < dwt2::kFusedRowsMax && cand[ncand] > 0) ncand++;
-        float best[dwt2::kFusedRowsMax][2];
-        for (int pass = 0; pass < 3; pass++)
-            for (int j = 0; j < 2 * ncand; j++) {
-                const int q = (j + pass * 2 * ncand / 3) % (2 * ncand), i = q / 2, o = q % 2;
-                float ms = 0.0f;
-                const int st = time_level(inverse, c, args, cand[i], kOrders[o], repeats, e0, e1, stream, &ms);
-                if (st != DWT2_OK) return st;
-                best[i][o] = pass == 0 ? ms : std::min(best[i][o], ms);
+        const int W = c.ws[k], H = c.hs[k];
+        // Every replay writes the same level output, so the next level reads
+        // this level's result.
+        run.exec.assign(ncand, nullptr);
+        run.graph.assign(ncand, nullptr);
+        for (int q = 0; q < ncand; q++) {
+            const hipError_t e = capture_level(inverse, c, args, cand[q / 2], kOrders[q % 2], repeats, run.s,
+                                               &run.graph[q], &run.exec[q]);
+            if (e != hipSuccess) return hip_status(e);
+        }
+        for (int q = 0; q < ncand; q++) {
+            const hipError_t e = hipGraphLaunch(run.exec[q], run.s);
+            if (e != hipSuccess) return hip_status(e);
+        }
+        float ms[2 * dwt2::kFusedRowsMax][kTunePasses];
+        for (int pass = 0; pass < kTunePasses; pass++)
+            for (int i = 0; i < ncand; i++) {
+                const int q = (i + pass) % ncand;
+                hipError_t e = hipEventRecord(run.e0, run.s);
+                if (e == hipSuccess) e = hipGraphLaunch(run.exec[q], run.s);
+                if (e == hipSuccess) e = hipEventRecord(run.e1, run.s);
+                if (e == hipSuccess) e = hipEventSynchronize(run.e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms[q][pass], run.e0, run.e1);
+                if (e != hipSuccess) return hip_status(e);
             }
-        int pick = 0, pick_o = 0;
-        for (int i = 0; i < dwt2::kFusedRowsMax && cand[i] > 0; i++)
-            for (int o = 0; o < 2; o++)
-                if (best[i][o] < best[pick][pick_o]) {
-                    pick = i;
-                    pick_o = o;
-                }
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        const TuneKey key{c.cfg.wavelet, inverse ? 1 : 0, c.ws[k], c.hs[k]};
-        if (g_tune.size() < kTuneMax || g_tune.count(key)) g_tune[key] = TuneVal{cand[pick], kOrders[pick_o]};
-        g_tune_size.store(g_tune.size(), std::memory_order_release);
+        float med[2 * dwt2::kFusedRowsMax], spread[2 * dwt2::kFusedRowsMax];
+        for (int q = 0; q < ncand; q++) {
+            float v[kTunePasses];
+            std::copy(ms[q], ms[q] + kTunePasses, v);
+            std::sort(v, v + kTunePasses);
+            med[q] = v[kTunePasses / 2];
+            spread[q] = v[kTunePasses - 1] - v[0];
+        }
+        const int rule_r = rule_rows(c.cfg.wavelet, W, H), rule_o = rule_order(W, H);
+        int ruleq = 0;
+        for (int q = 0; q < ncand; q++)
+            if (cand[q / 2] == rule_r && kOrders[q % 2] == rule_o) ruleq = q;
+        int best = 0;
+        for (int q = 1; q < ncand; q++)
+            if (med[q] < med[best]) best = q;
+        const int pick = med[best] < med[ruleq] - std::max(spread[best], spread[ruleq]) ? best : ruleq;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            const TuneKey key{c.cfg.wavelet, inverse ? 1 : 0, W, H};
+            if (g_tune.size() < kTuneMax || g_tune.count(key))
+                g_tune[key] = TuneVal{cand[pick / 2], kOrders[pick % 2]};
+            g_tune_size.store(g_tune.size(), std::memory_order_release);
+        }
+        run.release_graphs();  // the last replay has completed (event sync)
     }
     return DWT2_OK;
 }
@@ -806,15 +988,24 @@ DWT2_EXPORT int dwt2_autotune(int inverse, dwt2_wavelet wavelet, int levels, int
         c.cfg.tile_rows != 0 || c.cfg.lds_buffers != 0 || c.cfg.tile_order != 0 || c.cfg.fuse_tail != 0)
         return DWT2_E_UNSUPPORTED;
     if (repeats < 1 || repeats > 1000) return DWT2_E_ARG;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e == hipSuccess)
-        st = tune(inverse != 0, c, src, src_pitch, dst, dst_pitch, workspace, repeats, stream, e0, e1);
-    else
-        st = hip_status(e);
-    if (e1) (void)hipEventDestroy(e1);
-    if (e0) (void)hipEventDestroy(e0);
+    // The caller's earlier work (which may write src) completes first; the
+    // candidates then run on a private stream, and the call returns when
+    // they are done, with the result in dst.
+    hipError_t e = hipStreamSynchronize(stream);
+    TuneRun run;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&run.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&run.e0);
+    if (e == hipSuccess) e = hipEventCreate(&run.e1);
+    st = e == hipSuccess ? tune(inverse != 0, c, src, src_pitch, dst, dst_pitch, workspace, repeats, run)
+                         : hip_status(e);
+    if (run.s) {
+        const hipError_t es = hipStreamSynchronize(run.s);
+        if (st == DWT2_OK && es != hipSuccess) st = hip_status(es);
+    }
+    run.release_graphs();
+    if (run.e1) (void)hipEventDestroy(run.e1);
+    if (run.e0) (void)hipEventDestroy(run.e0);
+    if (run.s) (void)hipStreamDestroy(run.s);
     return st;
 }
 

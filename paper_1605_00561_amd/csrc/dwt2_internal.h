@@ -116,14 +116,41 @@ struct InvArgs {
     float quantum;
 };
 
-// Launch `kern` and return the status of this launch only (hipLaunchKernel
-// does not report errors left behind by earlier, unrelated HIP calls).
+// Test hook (dwt2_debug_fail_launches): true when the calling thread's next
+// launch is to fail without running; counts that launch down.
+bool take_launch_failure();
+
+// Launch `kern` with `lds` bytes of dynamic LDS and return the status of this
+// launch only (hipLaunchKernel does not report errors left behind by earlier,
+// unrelated HIP calls).
+template <typename... Args>
+inline hipError_t launch_lds(void (*kern)(Args...), dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                             Args... args)
+{
+    if (take_launch_failure()) return hipErrorInvalidConfiguration;
+    void *argv[] = {(void *)&args...};
+    return hipLaunchKernel((const void *)kern, grid, block, argv, lds, s);
+}
 template <typename... Args>
 inline hipError_t launch(void (*kern)(Args...), dim3 grid, dim3 block, hipStream_t s, Args... args)
 {
-    void *argv[] = {(void *)&args...};
-    return hipLaunchKernel((const void *)kern, grid, block, argv, 0, s);
+    return launch_lds(kern, grid, block, 0, s, args...);
 }
+
+// LDS poisoning (test builds with DWT2_POISON_LDS): every work-group fills
+// its LDS with NaN before its first LDS access, so a read of a cell that the
+// work-group has not written since it started shows in the results.
+#ifdef DWT2_POISON_LDS
+template <typename T>
+__device__ __forceinline__ void poison_lds(T *lds, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = (T)__builtin_nan("");
+    __syncthreads();
+}
+#else
+template <typename T>
+__device__ __forceinline__ void poison_lds(T *, int) {}
+#endif
 
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_tile_forward(int wavelet, int scheme, const FwdArgs &a, hipStream_t s);
@@ -200,10 +227,12 @@ static_assert(sizeof(BatchImage) == 64, "BatchImage is a 64-byte record");
 
 // One batched level.  `start` has count + 1 entries: the tiles of image i are
 // [start[i], start[i+1]) (empty when the image has no level k); start[count]
-// is the total.
+// is the total.  rows[i] is image i's tile height at this level, one of the
+// built heights of its wavelet (FP64 lifting: kFusedRowsFp64).
 struct BatchLevel {
     const BatchImage *imgs;
     const int *start;
+    const unsigned char *rows;
     int count, ntiles, level;
     Scale s[3];     // per wavelet: forward scales, or reciprocals for the inverse
     float ll_gain;
@@ -211,11 +240,16 @@ struct BatchLevel {
 };
 
 // Bytes of a batched call's workspace before the per-image LL buffers: the
-// image records and the tile-start table, each 256-byte aligned.
+// image records, the tile-start table and the tile-height table, each
+// 256-byte aligned.
 size_t batch_table_bytes(int count, int lmax);
 
-// Tile height of the batched launches, per wavelet.
-constexpr int kBatchRows[3] = {3, 4, 6};
+// Tallest built FP32 tile height of a wavelet (heights are listed ascending).
+constexpr int tallest_rows(int wavelet)
+{
+    return kFusedRows[wavelet][kFusedRowsMax - 1] > 0 ? kFusedRows[wavelet][kFusedRowsMax - 1]
+                                                      : kFusedRows[wavelet][kFusedRowsMax - 2];
+}
 // has_dd: the batch holds a DD 13/7 image (its taller tile needs more LDS).
 hipError_t launch_batch_forward(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s);
 hipError_t launch_batch_inverse(bool fp64, bool has_dd, const BatchLevel &b, hipStream_t s);
@@ -223,6 +257,23 @@ hipError_t launch_batch_inverse(bool fp64, bool has_dd, const BatchLevel &b, hip
 // kernels whose arguments carry the data: stream-ordered and capturable, and
 // the host buffer may be reused as soon as the call returns.
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// Transform-only launches (the measurement mode of Sec. 6 that leaves out the
+// image input and output): the level's grid of tiles, each synthesising its
+// samples in registers from its coordinates, lifting them exactly as the
+// scheme's level kernel does (every FMA, wavefront shift, LDS access and
+// barrier), and folding its results into a checksum that is stored to
+// sink[0] only if its bit pattern equals `key`.  The host passes a NaN
+// pattern that lifting finite samples never produces, so nothing is stored
+// and no image memory is touched, while no computation can be dropped.
+struct NoneArgs {
+    int W, H;
+    float *sink;
+    unsigned key;
+};
+hipError_t launch_fused_none(bool inverse, int wavelet, int rows, int buffers, int order,
+                             const NoneArgs &a, hipStream_t s);
+hipError_t launch_tile_none(bool inverse, int wavelet, int scheme, const NoneArgs &a, hipStream_t s);
 
 // Row-column: the intermediate `tmp` is W x H with pitch tmp_pitch.
 hipError_t launch_rowcol_forward(int wavelet, const FwdArgs &a, float *tmp, ptrdiff_t tmp_pitch,

@@ -40,7 +40,8 @@ EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_
            "dwt2_forward_batch", "dwt2_inverse_batch", "dwt2_server_create", "dwt2_server_submit",
            "dwt2_server_wait", "dwt2_server_replay", "dwt2_server_destroy", "dwt2_autotune",
            "dwt2_tile_rows", "dwt2_tile_order", "dwt2_tune_export", "dwt2_tune_import",
-           "dwt2_tune_reset"]
+           "dwt2_tune_reset", "dwt2_batch_tile_rows", "dwt2_transform_only",
+           "dwt2_debug_fail_launches"]
 BATCH_MAX = 65536
 # Tile heights the fused kernel is built for (FP32 lifting; FP64: one each).
 TILE_ROWS = {"cdf53": (2, 3), "cdf97": (2, 3, 4), "dd137": (3, 6)}
@@ -122,6 +123,10 @@ def _load() -> ctypes.CDLL:
     L.dwt2_inverse_batch.argtypes = L.dwt2_forward_batch.argtypes
     L.dwt2_batch_workspace_bytes.restype = i
     L.dwt2_forward_batch.restype = L.dwt2_inverse_batch.restype = i
+    L.dwt2_batch_tile_rows.argtypes = [i, ip, i, ctypes.POINTER(Options), i, ctypes.POINTER(i)]
+    L.dwt2_batch_tile_rows.restype = i
+    L.dwt2_transform_only.argtypes = [i, i, i, i, ctypes.POINTER(Options), vp, vp]
+    L.dwt2_transform_only.restype = i
     sp = ctypes.c_void_p  # dwt2_server *
     u64 = ctypes.c_ulonglong
     L.dwt2_server_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(ServerConfig), vp, sz,
@@ -139,6 +144,8 @@ def _load() -> ctypes.CDLL:
     L.dwt2_last_hip_error.restype = i
     L.dwt2_version.argtypes = []
     L.dwt2_version.restype = i
+    L.dwt2_debug_fail_launches.argtypes = [i]
+    L.dwt2_debug_fail_launches.restype = i
     L.dwt2_autotune.argtypes = [i, i, i, i, i, vp, pd, vp, pd, i, ctypes.POINTER(Options), vp, sz,
                                 i, vp]
     L.dwt2_tile_rows.argtypes = [i, i, i, i, ctypes.POINTER(Options), ctypes.POINTER(i)]
@@ -184,6 +191,10 @@ def dwt2_last_hip_error() -> int:
     return _lib.dwt2_last_hip_error()
 
 
+def dwt2_debug_fail_launches(count: int) -> int:
+    return _lib.dwt2_debug_fail_launches(int(count))
+
+
 def dwt2_workspace_bytes(wavelet, levels, width, height, opt: Options | None = None):
     """(status, bytes)."""
     n = ctypes.c_size_t(0)
@@ -204,6 +215,11 @@ def dwt2_inverse(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch,
     return _lib.dwt2_inverse(WAVELETS[wavelet], levels, width, height, src, src_pitch, dst,
                              dst_pitch, ext, ctypes.byref(opt) if opt is not None else None,
                              workspace, workspace_bytes, stream)
+
+
+def dwt2_transform_only(inverse, wavelet, width, height, opt: Options | None, sink, stream) -> int:
+    return _lib.dwt2_transform_only(int(bool(inverse)), WAVELETS[wavelet], width, height,
+                                    ctypes.byref(opt) if opt is not None else None, sink, stream)
 
 
 def dwt2_autotune(inverse, wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext,
@@ -267,6 +283,14 @@ def dwt2_batch_workspace_bytes(images, count, opt: Options | None = None):
                                          ctypes.byref(opt) if opt is not None else None,
                                          ctypes.byref(n))
     return st, n.value
+
+
+def dwt2_batch_tile_rows(inverse, images, count, level, opt: Options | None = None):
+    """(status, [rows per image]) of level `level` of a batched call."""
+    rows = (ctypes.c_int * max(count, 1))()
+    st = _lib.dwt2_batch_tile_rows(int(bool(inverse)), images, count,
+                                   ctypes.byref(opt) if opt is not None else None, level, rows)
+    return st, list(rows)[:count]
 
 
 def dwt2_forward_batch(images, count, ext, opt: Options | None, workspace, workspace_bytes,

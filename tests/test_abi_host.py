@@ -193,3 +193,71 @@ def test_single_hip_runtime_when_binding_is_imported_first():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_transform_only_argument_errors():
+    """dwt2_transform_only validates on the host like dwt2_forward (nothing
+    below is launched)."""
+    def call(inverse=0, wav="cdf97", w=64, h=64, opt=None, sink=FAKE):
+        return dwt2.dwt2_transform_only(inverse, wav, w, h, opt, sink, None)
+    assert call(sink=None) == dwt2.E_ARG
+    assert call(sink=FAKE + 2) == dwt2.E_ARG
+    assert call(w=0) == dwt2.E_ARG and call(h=-1) == dwt2.E_ARG
+    assert call(w=1) == dwt2.E_SIZE and call(h=1) == dwt2.E_SIZE
+    assert call(w=1 << 20, h=1 << 20) == dwt2.E_SIZE
+    assert call(opt=dwt2.make_options(arithmetic="fp64")) == dwt2.E_UNSUPPORTED
+    assert call(opt=dwt2.make_options(scheme="rowcol")) == dwt2.E_UNSUPPORTED
+    assert call(opt=dwt2.make_options(fuse_tail=1)) == dwt2.E_UNSUPPORTED
+    assert call(opt=dwt2.make_options(tile_rows=5)) == dwt2.E_UNSUPPORTED
+    assert call(wav="dd137", opt=dwt2.make_options(scheme="sweldens")) == dwt2.E_UNSUPPORTED
+    o = dwt2.make_options()
+    o.reserved[0] = 1
+    assert call(opt=o) == dwt2.E_ARG
+    assert dwt2.library().dwt2_transform_only(0, 7, 64, 64, None, FAKE, None) == dwt2.E_UNSUPPORTED
+
+
+def test_fault_injection_reaches_every_launching_entry_point():
+    """dwt2_debug_fail_launches makes the calling thread's next launches fail
+    with hipErrorInvalidConfiguration without launching, so each entry point's
+    DWT2_E_HIP path and dwt2_last_hip_error() are exercised on the host.  Every
+    call below fails at its first launch; nothing reaches the device."""
+    import threading
+    INVALID_CONFIGURATION = 9  # hipErrorInvalidConfiguration
+    lib = dwt2.library()
+    assert dwt2.dwt2_debug_fail_launches(-1) == dwt2.E_ARG
+    src, dst, ws = FAKE, FAKE + (1 << 26), FAKE + (1 << 28)
+    calls = [
+        lambda: dwt2.dwt2_forward("cdf97", 1, 64, 64, src, 64, dst, 64, 0, None, None, 0, None),
+        lambda: dwt2.dwt2_inverse("cdf53", 3, 64, 64, src, 64, dst, 64, 0, None, ws, 1 << 20, None),
+        lambda: dwt2.dwt2_forward("cdf53", 2, 64, 64, src, 64, dst, 64, 0,
+                                  dwt2.make_options(scheme="rowcol"), ws, 1 << 20, None),
+        lambda: dwt2.dwt2_forward("cdf97", 1, 64, 64, src, 64, dst, 64, 0,
+                                  dwt2.make_options(scheme="sweldens"), None, 0, None),
+        lambda: dwt2.dwt2_forward("dd137", 3, 100, 100, src, 100, dst, 100, 0,
+                                  dwt2.make_options(fuse_tail=1), ws, 1 << 20, None),
+        lambda: dwt2.dwt2_forward_batch(dwt2.make_images([("cdf97", 2, 64, 64, src, 64, dst, 64)]), 1,
+                                        0, None, ws, 1 << 20, None),
+        lambda: dwt2.dwt2_inverse_batch(dwt2.make_images([("cdf53", 1, 64, 64, src, 64, dst, 64)]), 1,
+                                        0, None, ws, 1 << 20, None),
+        lambda: dwt2.dwt2_transform_only(1, "cdf97", 64, 64, None, src, None),
+    ]
+    try:
+        assert dwt2.dwt2_debug_fail_launches(len(calls) + 2) == dwt2.OK
+        for i, call in enumerate(calls):
+            assert call() == dwt2.E_HIP, i
+            assert dwt2.dwt2_last_hip_error() == INVALID_CONFIGURATION, i
+        # the count is per thread: another thread's own count does not touch this one's
+        seen = []
+
+        def other():
+            dwt2.dwt2_debug_fail_launches(1)
+            seen.append((calls[0](), dwt2.dwt2_last_hip_error()))
+        t = threading.Thread(target=other)
+        t.start()
+        t.join()
+        assert seen == [(dwt2.E_HIP, INVALID_CONFIGURATION)]
+        for i in range(2):  # this thread's last two injected failures
+            assert calls[3]() == dwt2.E_HIP
+    finally:
+        dwt2.dwt2_debug_fail_launches(0)
+    assert lib.dwt2_debug_fail_launches(0) == dwt2.OK

@@ -39,7 +39,8 @@ def test_workspace_bytes_is_table_plus_each_images_ll_buffers():
            for (w, l, x, y) in [("cdf97", 3, 1000, 700), ("cdf53", 1, 64, 64),
                                 ("cdf53", 6, 999, 333)]]
     lmax = 6
-    assert ws_bytes(a, n) == _al(64 * n) + _al(4 * lmax * (n + 1)) + sum(per)
+    rows_table = _al(((n + 3) // 4 * 4) * lmax)  # one byte per image and level, rows of 4k bytes
+    assert ws_bytes(a, n) == _al(64 * n) + _al(4 * lmax * (n + 1)) + rows_table + sum(per)
     assert ws_bytes(a, 0) == 0
     # arithmetic and norm do not change the layout
     assert ws_bytes(a, n, arithmetic="fp64", norm="paper") == ws_bytes(a, n)
@@ -154,3 +155,97 @@ def test_tile_total_overflow_is_an_argument_error():
         assert st == status
     a, _ = images(img("cdf53", 1, side, side + 1))
     assert dwt2.dwt2_batch_workspace_bytes(a, 1, None)[0] == dwt2.E_SIZE
+
+
+# --- tile heights of batched calls (host-side plan; nothing is launched) -----
+TALLEST = {w: max(r) for w, r in dwt2.TILE_ROWS.items()}
+
+
+def tiles(wav, rows, w, h):
+    hq = {"cdf53": 1, "cdf97": 2, "dd137": 3}[wav]
+    ix, iy = 64 - 2 * hq, 4 * rows - 2 * hq
+    return -(-((w + 1) // 2) // ix) * -(-((h + 1) // 2) // iy)
+
+
+def model_rows(entries, level, tuned=None, fp64=False):
+    """The rule of dwt2_batch_tile_rows, written out: tuned sizes keep their
+    height; the others step down together from the tallest height until the
+    launch has 1024 tiles."""
+    tuned = tuned or {}
+    live = []
+    for (wav, lev, w, h, *_ ) in entries:
+        if lev <= level:
+            live.append(None)
+            continue
+        for _ in range(level):
+            w, h = (w + 1) // 2, (h + 1) // 2
+        live.append((wav, w, h))
+    if fp64:
+        return [0 if e is None else dwt2.TILE_ROWS_FP64[e[0]] for e in live]
+
+    def height(wav, step):
+        hs = dwt2.TILE_ROWS[wav]
+        return hs[max(0, len(hs) - 1 - step)]
+
+    def pick(step):
+        return [0 if e is None else tuned.get(e, height(e[0], step)) for e in live]
+
+    for step in range(3):
+        rows = pick(step)
+        if sum(tiles(e[0], r, e[1], e[2]) for e, r in zip(live, rows) if e) >= 1024:
+            return rows
+    return pick(2)
+
+
+def test_batch_tile_rows_follow_the_launch_fill_rule():
+    import numpy as np
+    rng = np.random.default_rng(40)
+    dwt2.dwt2_tune_reset()
+    for trial in range(60):
+        n = int(rng.integers(1, 12))
+        entries = []
+        for i in range(n):
+            w, h = int(rng.integers(2, 3000)), int(rng.integers(2, 3000))
+            wav = ("cdf53", "cdf97", "dd137")[int(rng.integers(0, 3))]
+            lev, ww, hh = 0, w, h
+            while lev < 6 and ww >= 2 and hh >= 2:
+                lev, ww, hh = lev + 1, (ww + 1) // 2, (hh + 1) // 2
+            entries.append(img(wav, int(rng.integers(1, lev + 1)), w, h,
+                               src=FAKE + (2 * i) * 64 * MiB, dst=FAKE + (2 * i + 1) * 64 * MiB))
+        a, _ = images(*entries)
+        for level in range(7):
+            for inverse in (0, 1):
+                st, rows = dwt2.dwt2_batch_tile_rows(inverse, a, n, level)
+                assert st == dwt2.OK
+                assert rows == model_rows(entries, level), (trial, level, entries)
+        st, rows = dwt2.dwt2_batch_tile_rows(0, a, n, 0, dwt2.make_options(arithmetic="fp64"))
+        assert st == dwt2.OK and rows == model_rows(entries, 0, fp64=True)
+
+
+def test_batch_tile_rows_take_tuned_heights():
+    entries = [img("cdf97", 3, 2000, 1500), img("cdf53", 2, 2000, 1800, src=FAKE + 128 * MiB,
+                                                  dst=FAKE + 192 * MiB)]
+    a, n = images(*entries)
+    try:
+        dwt2.dwt2_tune_reset()
+        st, rows = dwt2.dwt2_batch_tile_rows(0, a, n, 0)
+        assert st == dwt2.OK and rows == [TALLEST["cdf97"], TALLEST["cdf53"]]
+        # a forward entry for the 9/7 image's level 1 (1000 x 750) and an
+        # inverse one for the 5/3 image's level 1 (1000 x 900)
+        assert dwt2.dwt2_tune_import("1 0 1000 750 2 1\n0 1 1000 900 2 1\n") == dwt2.OK
+        fwd = {("cdf97", 1000, 750): 2}
+        inv = {("cdf53", 1000, 900): 2}
+        assert dwt2.dwt2_batch_tile_rows(0, a, n, 1)[1] == model_rows(entries, 1, fwd) == [2, 3]
+        # the inverse launch of level 1 is short of work-groups: the untuned
+        # 9/7 image steps down, the tuned 5/3 image keeps its height
+        assert dwt2.dwt2_batch_tile_rows(1, a, n, 1)[1] == model_rows(entries, 1, inv) == [3, 2]
+        assert dwt2.dwt2_batch_tile_rows(1, a, n, 0)[1] == model_rows(entries, 0, inv)
+        assert dwt2.dwt2_batch_tile_rows(0, a, n, 2)[1][1] == 0  # the 5/3 image has 2 levels
+        # FP64 lifting has one height per wavelet, tuned or not
+        st, rows = dwt2.dwt2_batch_tile_rows(0, a, n, 1, dwt2.make_options(arithmetic="fp64"))
+        assert rows == [dwt2.TILE_ROWS_FP64["cdf97"], dwt2.TILE_ROWS_FP64["cdf53"]]
+    finally:
+        dwt2.dwt2_tune_reset()
+    assert dwt2.dwt2_batch_tile_rows(0, a, n, -1)[0] == dwt2.E_ARG
+    assert dwt2.dwt2_batch_tile_rows(0, a, n, 0, dwt2.make_options(tile_rows=3))[0] == \
+        dwt2.E_UNSUPPORTED

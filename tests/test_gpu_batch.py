@@ -145,3 +145,53 @@ def test_full_batch_of_512_uneven_images():
         check(got, ref, False, f"fwd batch image {i} {w}x{h} {wav} L{lev}")
         check(to_host(zs[i]), oracle.inverse(got, wav, lev, "unit_dc"), False,
               f"inv batch image {i}")
+
+
+def test_batch_at_tuned_and_stepped_down_heights():
+    """Images whose level sizes have tuned heights (every built height is
+    used by some image level) and small batches whose launches step down to
+    shorter tiles: every image still equals its single-image call bit for
+    bit, and the small ones the oracle."""
+    xs, hosts = mixed_inputs(203)
+    wavs, levs = [m[2] for m in MIXED], [m[3] for m in MIXED]
+    lines = []
+    for (w, h, wav, lev, _) in MIXED:
+        heights = dwt2.TILE_ROWS[wav]
+        for k in range(lev):
+            for inv in (0, 1):
+                lines.append(f"{dwt2.WAVELETS[wav]} {inv} {w} {h} {heights[(k + inv) % len(heights)]} 1")
+            w, h = (w + 1) // 2, (h + 1) // 2
+    try:
+        dwt2.dwt2_tune_reset()
+        assert dwt2.dwt2_tune_import("\n".join(lines) + "\n") == dwt2.OK
+        a = dwt2.make_images([(wav, lev, x.shape[1], x.shape[0], x.data_ptr(), x.stride(0),
+                               x.data_ptr() + 4, x.stride(0))
+                              for x, wav, lev in zip(xs, wavs, levs)])
+        used = set()
+        for k in range(max(levs)):
+            st, rows = dwt2.dwt2_batch_tile_rows(0, a, len(xs), k)
+            assert st == dwt2.OK
+            used |= {(wavs[i], r) for i, r in enumerate(rows) if r}
+        assert used == {(w, r) for w in set(wavs) for r in dwt2.TILE_ROWS[w]}
+        ys = dwt2.forward_batch(xs, wavs, levs, outs=outs_like(xs))
+        zs = dwt2.inverse_batch(ys, wavs, levs, outs=outs_like(xs))
+        torch.cuda.synchronize()
+    finally:
+        dwt2.dwt2_tune_reset()
+    for i, (x, y, z, wav, lev) in enumerate(zip(xs, ys, zs, wavs, levs)):
+        what = f"image {i} {x.shape[1]}x{x.shape[0]} {wav} L{lev}"
+        assert torch.equal(y, single(x, wav, lev, "unit_dc", "auto")), "forward " + what
+        assert torch.equal(z, single(y, wav, lev, "unit_dc", "auto", inverse=True)), "inverse " + what
+        got = to_host(y)
+        check(got, oracle.forward(hosts[i].astype(np.float64), wav, lev), exact_expected(wav, lev, "unit_dc"),
+              "fwd " + what)
+    # two small images: every level launch is short of work-groups
+    for sub in ([0, 2], [3, 11]):
+        st, rows = dwt2.dwt2_batch_tile_rows(0, dwt2.make_images(
+            [(wavs[i], levs[i], xs[i].shape[1], xs[i].shape[0], 1 << 40, xs[i].stride(0),
+              1 << 41, xs[i].stride(0)) for i in sub]), len(sub), 0)
+        assert rows == [min(dwt2.TILE_ROWS[wavs[i]]) for i in sub]
+        ys = dwt2.forward_batch([xs[i] for i in sub], [wavs[i] for i in sub], [levs[i] for i in sub])
+        torch.cuda.synchronize()
+        for j, i in enumerate(sub):
+            assert torch.equal(ys[j], single(xs[i], wavs[i], levs[i], "unit_dc", "auto")), f"small {i}"
