@@ -257,6 +257,29 @@ int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int height,
                  size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Allocation-free transform, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): dwt2_forward (inverse == 0) or dwt2_inverse (inverse != 0)
+ * with the same arguments except the workspace, which is a device array of
+ * DWT2_NOALLOC_SCRATCH_BYTES inside the library (each device the library
+ * runs on holds its own copy until the process ends).  The call allocates
+ * nothing and frees nothing; on its first use on a device it looks up that
+ * device's copy (a HIP symbol query, no allocation).  A call whose
+ * dwt2_workspace_bytes() exceeds DWT2_NOALLOC_SCRATCH_BYTES returns
+ * DWT2_E_WORKSPACE and enqueues nothing (one-level calls need no workspace,
+ * so any size works; two levels up to 8192 x 8192; deeper ones up to about
+ * 50 Mpixel, e.g. 7000 x 7000).  Every call on a device shares that device's array: calls
+ * that overlap in time on one device (on different streams, or from threads
+ * whose streams are not ordered) race on it and give wrong results; calls
+ * ordered on one stream do not.  The array needs no clearing: every call
+ * writes the workspace before reading it.  Statuses as dwt2_forward.
+ */
+#define DWT2_NOALLOC_SCRATCH_BYTES 67108864 /* 64 MiB */
+int dwt2_transform_noalloc(int inverse, dwt2_wavelet wavelet, int levels, int width, int height,
+                           const float *src, ptrdiff_t src_pitch, float *dst, ptrdiff_t dst_pitch,
+                           dwt2_ext ext, const dwt2_options *opt, hipStream_t stream);
+
+/*
  * Transform-only measurement (the paper's Sec. 6 mode that leaves out the
  * input and output of data, used by its Experiments 1 and 2).  Enqueues one
  * level of the forward (inverse == 0) or inverse transform of a width x height

@@ -505,6 +505,66 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
     return DWT2_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free calls: the workspace is a file-scope device array of
+// DWT2_NOALLOC_SCRATCH_BYTES.  Host code never uses the array's name as an
+// address: its device address is looked up once per device (with that device
+// current) and kept in g_scratch.
+
+namespace {
+
+__device__ __align__(256) unsigned char scratch[DWT2_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<void *> g_scratch[kMaxDevices];
+
+// The current device's scratch address, looked up on its first use.
+int scratch_of_current_device(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e);
+    if (dev < 0 || dev >= kMaxDevices) return DWT2_E_UNSUPPORTED;
+    void *p = g_scratch[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        p = g_scratch[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return hip_status(e);
+            if (!p) return DWT2_E_HIP;
+            g_scratch[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return DWT2_OK;
+}
+
+}  // namespace
+
+DWT2_EXPORT int dwt2_transform_noalloc(int inverse, dwt2_wavelet wavelet, int levels, int width,
+                                       int height, const float *src, ptrdiff_t src_pitch, float *dst,
+                                       ptrdiff_t dst_pitch, dwt2_ext ext, const dwt2_options *opt,
+                                       hipStream_t stream)
+{
+    Checked c;
+    int st = check_call(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext, opt, nullptr, 0,
+                        &c, false);
+    if (st != DWT2_OK) return st;
+    const size_t need = c.lay.total;
+    if (need > (size_t)DWT2_NOALLOC_SCRATCH_BYTES) return DWT2_E_WORKSPACE;
+    void *ws = nullptr;
+    if (need > 0) {
+        st = scratch_of_current_device(&ws);
+        if (st != DWT2_OK) return st;
+    }
+    return inverse ? dwt2_inverse(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext, opt, ws,
+                                  need, stream)
+                   : dwt2_forward(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch, ext, opt, ws,
+                                  need, stream);
+}
+
 DWT2_EXPORT int dwt2_transform_only(int inverse, dwt2_wavelet wavelet, int width, int height,
                                     const dwt2_options *opt, float *sink, hipStream_t stream)
 {

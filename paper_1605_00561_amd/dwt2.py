@@ -41,7 +41,7 @@ EXPORTS = ["dwt2_forward", "dwt2_inverse", "dwt2_workspace_bytes", "dwt2_status_
            "dwt2_server_wait", "dwt2_server_replay", "dwt2_server_destroy", "dwt2_autotune",
            "dwt2_tile_rows", "dwt2_tile_order", "dwt2_tune_export", "dwt2_tune_import",
            "dwt2_tune_reset", "dwt2_batch_tile_rows", "dwt2_transform_only",
-           "dwt2_debug_fail_launches"]
+           "dwt2_transform_noalloc", "dwt2_debug_fail_launches"]
 BATCH_MAX = 65536
 # Tile heights the fused kernel is built for (FP32 lifting; FP64: one each).
 TILE_ROWS = {"cdf53": (2, 3), "cdf97": (2, 3, 4), "dd137": (3, 6)}
@@ -127,6 +127,8 @@ def _load() -> ctypes.CDLL:
     L.dwt2_batch_tile_rows.restype = i
     L.dwt2_transform_only.argtypes = [i, i, i, i, ctypes.POINTER(Options), vp, vp]
     L.dwt2_transform_only.restype = i
+    L.dwt2_transform_noalloc.argtypes = [i, i, i, i, i, vp, pd, vp, pd, i, ctypes.POINTER(Options), vp]
+    L.dwt2_transform_noalloc.restype = i
     sp = ctypes.c_void_p  # dwt2_server *
     u64 = ctypes.c_ulonglong
     L.dwt2_server_create.argtypes = [ctypes.POINTER(Options), ctypes.POINTER(ServerConfig), vp, sz,
@@ -215,6 +217,16 @@ def dwt2_inverse(wavelet, levels, width, height, src, src_pitch, dst, dst_pitch,
     return _lib.dwt2_inverse(WAVELETS[wavelet], levels, width, height, src, src_pitch, dst,
                              dst_pitch, ext, ctypes.byref(opt) if opt is not None else None,
                              workspace, workspace_bytes, stream)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def dwt2_transform_noalloc(inverse, wavelet, levels, width, height, src, src_pitch, dst, dst_pitch,
+                           ext, opt: Options | None, stream) -> int:
+    return _lib.dwt2_transform_noalloc(int(bool(inverse)), WAVELETS[wavelet], levels, width, height,
+                                       src, src_pitch, dst, dst_pitch, ext,
+                                       ctypes.byref(opt) if opt is not None else None, stream)
 
 
 def dwt2_transform_only(inverse, wavelet, width, height, opt: Options | None, sink, stream) -> int:

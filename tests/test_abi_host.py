@@ -216,6 +216,31 @@ def test_transform_only_argument_errors():
     assert dwt2.library().dwt2_transform_only(0, 7, 64, 64, None, FAKE, None) == dwt2.E_UNSUPPORTED
 
 
+def test_noalloc_argument_errors():
+    """dwt2_transform_noalloc validates everything but the workspace (its own
+    static array) on the host first, and refuses a workspace need beyond the
+    array before touching the device."""
+    def call(wav="cdf97", lev=2, w=64, h=64, src=FAKE, sp=64, dst=FAKE + (1 << 26), dp=64, opt=None,
+             inverse=0):
+        return dwt2.dwt2_transform_noalloc(inverse, wav, lev, w, h, src, sp, dst, dp, 0, opt, None)
+    for inverse in (0, 1):
+        assert call(src=None, inverse=inverse) == dwt2.E_ARG
+        assert call(sp=10, inverse=inverse) == dwt2.E_ARG
+        assert call(lev=0, inverse=inverse) == dwt2.E_ARG
+        assert call(lev=8, inverse=inverse) == dwt2.E_SIZE
+        assert call(dst=FAKE + 4, inverse=inverse) == dwt2.E_ALIAS
+        bad = dwt2.make_options()
+        bad.scheme = 99
+        assert call(opt=bad, inverse=inverse) == dwt2.E_UNSUPPORTED
+        big = dict(w=8192, h=8192, sp=8192, dp=8192, dst=FAKE + (1 << 30), lev=3)
+        assert call(inverse=inverse, **big) == dwt2.E_WORKSPACE  # 64 + 16 MiB of LL buffers
+        assert call(inverse=inverse, opt=dwt2.make_options(scheme="rowcol"), w=4096, h=4096, sp=4096,
+                    dp=4096, dst=FAKE + (1 << 30)) == dwt2.E_WORKSPACE  # + 64 MiB intermediate
+    assert header_define("DWT2_NOALLOC_SCRATCH_BYTES") == dwt2.NOALLOC_SCRATCH_BYTES
+    assert dwt2.dwt2_workspace_bytes("cdf97", 3, 8192, 8192)[1] > dwt2.NOALLOC_SCRATCH_BYTES
+    assert dwt2.dwt2_workspace_bytes("cdf97", 2, 8192, 8192)[1] == dwt2.NOALLOC_SCRATCH_BYTES
+
+
 def test_fault_injection_reaches_every_launching_entry_point():
     """dwt2_debug_fail_launches makes the calling thread's next launches fail
     with hipErrorInvalidConfiguration without launching, so each entry point's
@@ -240,6 +265,7 @@ def test_fault_injection_reaches_every_launching_entry_point():
         lambda: dwt2.dwt2_inverse_batch(dwt2.make_images([("cdf53", 1, 64, 64, src, 64, dst, 64)]), 1,
                                         0, None, ws, 1 << 20, None),
         lambda: dwt2.dwt2_transform_only(1, "cdf97", 64, 64, None, src, None),
+        lambda: dwt2.dwt2_transform_noalloc(0, "cdf53", 1, 64, 64, src, 64, dst, 64, 0, None, None),
     ]
     try:
         assert dwt2.dwt2_debug_fail_launches(len(calls) + 2) == dwt2.OK
