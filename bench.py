@@ -72,6 +72,10 @@ def parse():
                     help="skip the serving-loop request stream")
     ap.add_argument("--no-tiles", action="store_true",
                     help="skip the tile-height table (every built height per wavelet and size)")
+    ap.add_argument("--no-transform-only", action="store_true",
+                    help="skip the transform-only table (no image I/O, every scheme)")
+    ap.add_argument("--no-c1", action="store_true",
+                    help="skip the 512^2 5/3 one-level table")
     ap.add_argument("--no-copy", action="store_true",
                     help="skip the device-to-device copy (the bandwidth and counter reference)")
     return ap.parse_args()
@@ -263,8 +267,9 @@ def main():
         out["schemes"] = scheme_table(dwt2, torch, xs, ys, zs, wav, lev, npx, args.scheme_reps)
     if not args.no_tiles:
         out["tiles"] = tile_table(dwt2, torch, xs[0], ys[0], zs[0], args.scheme_reps)
-    if not args.no_schemes:
+    if not args.no_transform_only:
         out["transform_only"] = transform_only_table(dwt2, torch, dev)
+    if not args.no_c1:
         out["c1_512"] = c1_table(dwt2, torch, workloads, dev)
     if not args.no_pyramid:
         del xs, ys, zs

@@ -629,7 +629,8 @@ bool any_write_overlap(std::vector<Interval> &v)
 struct BatchPlan {
     Config cfg;
     int lmax = 0;
-    size_t rec_off = 0, tab_off = 0, rows_off = 0, total = 0;
+    size_t rec_off = 0, tab_off = 0, rows_off = 0, idx_off = 0, total = 0;
+    long long idx_level_off[dwt2::kBatchMaxLevels] = {};  // tiles before level k in the index
     std::vector<dwt2::BatchImage> rec;  // buffers as offsets until bound to a workspace
     std::vector<size_t> buf_off[2];
     std::vector<int> start;             // lmax x (count + 1)
@@ -706,6 +707,8 @@ long long batch_level_rows(const BatchPlan &p, bool inverse, int k, unsigned cha
 int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_options *opt,
                bool inverse, BatchPlan *p)
 {
+    static_assert(DWT2_BATCH_MAX <= 65536, "image numbers in the tile-image index are 16-bit");
+    static_assert(kMaxLevels <= dwt2::kBatchMaxLevels, "levels of the tile-image index");
     if (count < 0 || count > DWT2_BATCH_MAX || (count > 0 && !images)) return DWT2_E_ARG;
     int st = parse(DWT2_CDF53, ext, opt, &p->cfg);
     if (st != DWT2_OK) return st;
@@ -749,10 +752,22 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
         p->lmax = std::max(p->lmax, im.levels);
     }
     // Tile heights and starts per level; every level's total must index with
-    // an int.
+    // an int.  The tile-image index is sized for every image's tiles at its
+    // wavelet's shortest height (an upper bound whatever heights a call
+    // picks, so the workspace size does not depend on the direction or the
+    // tuned table); the levels' index regions follow each other.
     const size_t rs = rows_stride(count);
     p->start.assign((size_t)p->lmax * (count + 1), 0);
     p->rows.assign((size_t)p->lmax * rs, 0);
+    long long idx_bound = 0, idx_used = 0;
+    for (int i = 0; i < count; i++) {
+        const dwt2::BatchImage &r = p->rec[i];
+        for (int k = 0; k < r.levels; k++) {
+            const int w = (int)(((long long)r.W + (1LL << k) - 1) >> k);
+            const int h = (int)(((long long)r.H + (1LL << k) - 1) >> k);
+            idx_bound += dwt2::fused_tile_count(r.wavelet, dwt2::kFusedRows[r.wavelet][0], w, h);
+        }
+    }
     for (int k = 0; k < p->lmax; k++) {
         unsigned char *rows = &p->rows[(size_t)k * rs];
         if (batch_level_rows(*p, inverse, k, rows) > INT_MAX - 8) return DWT2_E_ARG;
@@ -768,11 +783,15 @@ int plan_batch(const dwt2_image *images, int count, dwt2_ext ext, const dwt2_opt
             }
         }
         s[count] = (int)acc;
+        p->idx_level_off[k] = idx_used;
+        idx_used += acc;
     }
+    if (idx_used > idx_bound) return DWT2_E_ARG;  // not reached: heights >= the shortest
     p->rec_off = 0;
     p->tab_off = align_up(sizeof(dwt2::BatchImage) * (size_t)count);
     p->rows_off = p->tab_off + align_up(sizeof(int) * (size_t)p->lmax * (size_t)(count + 1));
-    const size_t img_base = dwt2::batch_table_bytes(count, p->lmax);
+    p->idx_off = dwt2::batch_table_bytes(count, p->lmax);
+    const size_t img_base = p->idx_off + align_up(sizeof(unsigned short) * (size_t)idx_bound);
     for (int i = 0; i < count; i++) {
         p->buf_off[0][i] += img_base;
         p->buf_off[1][i] += img_base;
@@ -811,6 +830,15 @@ int run_batch(bool inverse, const dwt2_image *images, int count, dwt2_ext ext,
     if (e == hipSuccess)
         e = dwt2::launch_upload(wsb + p.tab_off, p.start.data(), sizeof(int) * p.start.size(), stream);
     if (e == hipSuccess) e = dwt2::launch_upload(wsb + p.rows_off, p.rows.data(), p.rows.size(), stream);
+    if (e == hipSuccess) {
+        dwt2::BatchIndexArgs ia = {};
+        ia.start = (const int *)(wsb + p.tab_off);
+        ia.index = (unsigned short *)(wsb + p.idx_off);
+        ia.count = count;
+        ia.lmax = p.lmax;
+        std::copy(p.idx_level_off, p.idx_level_off + p.lmax, ia.off);
+        e = dwt2::launch_batch_index(ia, stream);
+    }
     if (e != hipSuccess) return hip_status(e);
 
     dwt2::BatchLevel b;
@@ -828,6 +856,7 @@ int run_batch(bool inverse, const dwt2_image *images, int count, dwt2_ext ext,
         b.level = k;
         b.start = (const int *)(wsb + p.tab_off) + (size_t)k * (count + 1);
         b.rows = (const unsigned char *)(wsb + p.rows_off) + (size_t)k * rows_stride(count);
+        b.tile_image = (const unsigned short *)(wsb + p.idx_off) + p.idx_level_off[k];
         b.ntiles = p.start[(size_t)k * (count + 1) + count];
         b.quantum = norm == DWT2_NORM_PAPER ? ldexpf(1.0f, k) : 1.0f;
         e = inverse ? dwt2::launch_batch_inverse(fp64, has_dd, b, stream)

@@ -227,11 +227,14 @@ static_assert(sizeof(BatchImage) == 64, "BatchImage is a 64-byte record");
 
 // One batched level.  `start` has count + 1 entries: the tiles of image i are
 // [start[i], start[i+1]) (empty when the image has no level k); start[count]
-// is the total.  rows[i] is image i's tile height at this level, one of the
-// built heights of its wavelet (FP64 lifting: kFusedRowsFp64).
+// is the total.  tile_image[t] is the image of tile t (written on the device
+// by k_batch_index from `start`).  rows[i] is image i's tile height at this
+// level, one of the built heights of its wavelet (FP64 lifting:
+// kFusedRowsFp64).
 struct BatchLevel {
     const BatchImage *imgs;
     const int *start;
+    const unsigned short *tile_image;
     const unsigned char *rows;
     int count, ntiles, level;
     Scale s[3];     // per wavelet: forward scales, or reciprocals for the inverse
@@ -239,10 +242,23 @@ struct BatchLevel {
     float quantum;
 };
 
-// Bytes of a batched call's workspace before the per-image LL buffers: the
-// image records, the tile-start table and the tile-height table, each
-// 256-byte aligned.
+// Bytes of a batched call's workspace before the tile-image index and the
+// per-image LL buffers: the image records, the tile-start table and the
+// tile-height table, each 256-byte aligned.
 size_t batch_table_bytes(int count, int lmax);
+
+// Tile-image index of a batched call: for each level k, the image of every
+// tile of that level's launch, as 16-bit image numbers (count <= 65536), at
+// offset off[k] tiles into the index.  k_batch_index fills it from the
+// tile-start table, one work-group per (image, level).
+constexpr int kBatchMaxLevels = 32;
+struct BatchIndexArgs {
+    const int *start;       // lmax x (count + 1)
+    unsigned short *index;  // the index
+    int count, lmax;
+    long long off[kBatchMaxLevels];
+};
+hipError_t launch_batch_index(const BatchIndexArgs &a, hipStream_t s);
 
 // Tallest built FP32 tile height of a wavelet (heights are listed ascending).
 constexpr int tallest_rows(int wavelet)

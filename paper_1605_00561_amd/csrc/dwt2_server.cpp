@@ -65,7 +65,7 @@ using dwt2::serve::Group;
 struct Pending {
     unsigned long long ticket;
     dwt2_request r;
-    size_t ll_bytes;  // the image's own LL buffers in a batch workspace
+    size_t ll_bytes;  // the image's own part of a batch workspace (index entries, LL buffers)
     Clock::time_point submitted;
 };
 
@@ -264,11 +264,12 @@ int request_footprint(const dwt2_server *s, const dwt2_request *r, size_t *ll_by
     const dwt2_image im = {r->wavelet, r->levels, r->width, r->height, r->src, r->src_pitch,
                            r->dst, r->dst_pitch};
     size_t one = 0;
-    int st = dwt2_batch_workspace_bytes(&im, 1, &s->opt, &one);
+    const int st = dwt2_batch_workspace_bytes(&im, 1, &s->opt, &one);
     if (st != DWT2_OK) return st;
-    st = dwt2_workspace_bytes((dwt2_wavelet)r->wavelet, r->levels, r->width, r->height, &s->opt,
-                              ll_bytes);
-    if (st != DWT2_OK) return st;
+    // The request's own part of any batch workspace (its tile-image index
+    // entries and LL buffers, each rounded up to 256 bytes, so the parts of a
+    // batch's requests add up to at least what the batch lays out).
+    *ll_bytes = one - dwt2::batch_table_bytes(1, r->levels);
     const uintptr_t s0 = (uintptr_t)r->src, d0 = (uintptr_t)r->dst, a0 = (uintptr_t)s->arena;
     const uintptr_t s1 = s0 + span_bytes(r->src_pitch, r->width, r->height);
     const uintptr_t d1 = d0 + span_bytes(r->dst_pitch, r->width, r->height);

@@ -707,25 +707,21 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_tail_inverse(TailArgs t)
     }
 }
 
-// Batched levels.  A work-group finds its image by a search over the tile
-// starts that costs one coalesced load per 64-fold narrowing (two for up to
-// 4096 images), then runs the same tile body as the single-image kernel, so
-// every image gets the bits the single-image call gives it.
-__device__ __forceinline__ int find_image(const int *__restrict__ start, int count, int t)
+// Batched levels.  A work-group reads its tile's image from the tile-image
+// index (two bytes, in a cache line shared with 63 neighbouring tiles), then
+// runs the same tile body as the single-image kernel, so every image gets the
+// bits the single-image call gives it.  (A search over the tile starts instead
+// touched 17 cache lines per work-group for 512 images, and a wider one-round
+// search 128: at ~900,000 work-groups per level that request traffic, not the
+// search's latency, measurably slowed the launch.)
+__global__ __launch_bounds__(256) void k_batch_index(BatchIndexArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    int lo = 0, hi = count;  // start[lo] <= t, and start[hi] > t unless hi == count
-    while (hi - lo > 1) {
-        const int step = (hi - lo + 63) / 64;
-        const int idx = lo + lane * step;
-        const bool le = idx < hi && start[idx] <= t;  // true on a prefix of the lanes
-        const int m = __popcll(__ballot(le)) - 1;     // lane 0 is always true
-        lo = __builtin_amdgcn_readfirstlane(lo + m * step);
-        hi = min(lo + step, hi);
-    }
-    return lo;
+    const int i = blockIdx.x, k = blockIdx.y;
+    const int *start = a.start + (size_t)k * (a.count + 1);
+    const int s0 = start[i], n = start[i + 1] - s0;
+    unsigned short *idx = a.index + a.off[k] + s0;
+    for (int j = threadIdx.x; j < n; j += 256) idx[j] = (unsigned short)i;
 }
-
 
 // One tile of image level `a` at height RB, given the tile's index within the
 // image.
@@ -799,7 +795,7 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_forward(BatchLevel b)
     const int t = xcd_tile(b.ntiles);
     if (t < 0) return;
     poison_lds(sm, (int)(sizeof(sm) / sizeof(sm[0])));
-    const int i = find_image(b.start, b.count, t);
+    const int i = b.tile_image[t];
     const BatchImage &im = b.imgs[i];
     const int k = b.level, last = im.levels - 1;
     const int W = level_size(im.W, k), H = level_size(im.H, k);
@@ -829,7 +825,7 @@ __global__ __launch_bounds__(NTHREADS) void k_batch_inverse(BatchLevel b)
     const int t = xcd_tile(b.ntiles);
     if (t < 0) return;
     poison_lds(sm, (int)(sizeof(sm) / sizeof(sm[0])));
-    const int i = find_image(b.start, b.count, t);
+    const int i = b.tile_image[t];
     const BatchImage &im = b.imgs[i];
     const int k = b.level, last = im.levels - 1;
     const int W = level_size(im.W, k), H = level_size(im.H, k);
@@ -1105,6 +1101,12 @@ hipError_t launch_batch_inverse(bool fp64, bool has_dd, const BatchLevel &b, hip
                     : launch(k_batch_inverse<float, true>, grid, block, s, b);
     return fp64 ? launch(k_batch_inverse<double, false>, grid, block, s, b)
                 : launch(k_batch_inverse<float, false>, grid, block, s, b);
+}
+
+hipError_t launch_batch_index(const BatchIndexArgs &a, hipStream_t s)
+{
+    if (a.count <= 0 || a.lmax <= 0 || a.lmax > kBatchMaxLevels || a.count > 65536) return hipErrorInvalidValue;
+    return launch(k_batch_index, dim3(a.count, a.lmax), dim3(256), s, a);
 }
 
 hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t s)

@@ -12,7 +12,9 @@
 // Rows pass: one wavefront per row segment, two lifting pairs (four samples)
 // per lane, neighbours exchanged with wave shuffles; K pairs of halo per side.
 // Cols pass: one lane per column, streaming down a segment of rows with a
-// register pipeline of K stages (each stage = one predict/update pair).
+// register pipeline of K stages (each stage = one predict/update pair); the
+// segment is shorter on small levels, so that they still have enough
+// work-groups.
 #include "dwt2_internal.h"
 
 namespace dwt2 {
@@ -21,7 +23,21 @@ namespace {
 constexpr int RT = 256;           // threads per block
 constexpr int RW = 4;             // waves per block (rows pass: one row each)
 constexpr int NPW = 128;          // lifting pairs per wave in the rows pass
-constexpr int CSEG = 64;          // output pairs per column segment
+constexpr int CSEG = 64;          // output pairs per column segment (large levels)
+constexpr int CSEG_MIN = 8;       // shortest segment (small levels)
+constexpr int kColBlocks = 1024;  // column work-groups a level should have (four per CU)
+
+// Column segment length: CSEG, halved down to CSEG_MIN while the column grid
+// has fewer than kColBlocks work-groups.  Each segment re-reads 2K halo
+// pairs, so short segments cost reads; a small level is latency-bound
+// instead (each lane streams its segment one pair after another).
+int col_segment(int W, int QH)
+{
+    const long long gx = (W + RT - 1) / RT;
+    int seg = CSEG;
+    while (seg > CSEG_MIN && gx * ((QH + seg - 1) / seg) < kColBlocks) seg /= 2;
+    return seg;
+}
 
 // ---------------------------------------------------------------------------
 // Rows pass, forward: in (W x H) -> tmp [L | H]
@@ -106,7 +122,7 @@ __global__ __launch_bounds__(RT) void k_rows_inverse(const float *tmp, ptrdiff_t
 // Pipeline stage k keeps the pending pair (Lk, Hk) and its previous output H.
 // ---------------------------------------------------------------------------
 template <int WAV>
-__global__ __launch_bounds__(RT) void k_cols_forward(const float *tmp, ptrdiff_t tmp_pitch, FwdArgs a)
+__global__ __launch_bounds__(RT) void k_cols_forward(const float *tmp, ptrdiff_t tmp_pitch, FwdArgs a, int cseg)
 {
     using L = Lift<WAV>;
     constexpr int K = L::K;
@@ -114,7 +130,7 @@ __global__ __launch_bounds__(RT) void k_cols_forward(const float *tmp, ptrdiff_t
     const int W = a.W, H = a.H;
     if (c >= W) return;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1, HH_ = H >> 1;
-    const int r0 = blockIdx.y * CSEG, r1 = min(r0 + CSEG, QH);
+    const int r0 = blockIdx.y * cseg, r1 = min(r0 + cseg, QH);
     const bool lowcol = c < QW;  // column of the horizontal L half
     const float sl = lowcol ? a.s.ll : 1.0f, sh = lowcol ? 1.0f : a.s.hh;
     float *lo_base = lowcol ? a.ll : a.det;
@@ -161,7 +177,7 @@ __global__ __launch_bounds__(RT) void k_cols_forward(const float *tmp, ptrdiff_t
 // and emits (L'_t, H'_t).  State: previous L' and the pending input H.
 // ---------------------------------------------------------------------------
 template <int WAV>
-__global__ __launch_bounds__(RT) void k_cols_inverse(InvArgs a, float *tmp, ptrdiff_t tmp_pitch)
+__global__ __launch_bounds__(RT) void k_cols_inverse(InvArgs a, float *tmp, ptrdiff_t tmp_pitch, int cseg)
 {
     using L = Lift<WAV>;
     constexpr int K = L::K;
@@ -169,7 +185,7 @@ __global__ __launch_bounds__(RT) void k_cols_inverse(InvArgs a, float *tmp, ptrd
     const int W = a.W, H = a.H;
     if (c >= W) return;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1;
-    const int r0 = blockIdx.y * CSEG, r1 = min(r0 + CSEG, QH);
+    const int r0 = blockIdx.y * cseg, r1 = min(r0 + cseg, QH);
     const bool lowcol = c < QW;
     const float sl = lowcol ? a.inv_s.ll : 1.0f, sh = lowcol ? 1.0f : a.inv_s.hh;
     const float *lo_base = lowcol ? a.ll : a.det;
@@ -216,16 +232,17 @@ hipError_t launch_rowcol_forward(int wavelet, const FwdArgs &a, float *tmp, ptrd
 {
     const int K = wavelet == CDF97 ? 2 : 1;
     const int QW = (a.W + 1) / 2, QH = (a.H + 1) / 2;
+    const int cseg = col_segment(a.W, QH);
     const dim3 rg((QW + NPW - 2 * K - 1) / (NPW - 2 * K), (a.H + RW - 1) / RW);
-    const dim3 cg((a.W + RT - 1) / RT, (QH + CSEG - 1) / CSEG);
+    const dim3 cg((a.W + RT - 1) / RT, (QH + cseg - 1) / cseg);
     hipError_t e = hipErrorInvalidValue;
     const float *ct = tmp;
     if (wavelet == CDF53) {
         e = launch(k_rows_forward<CDF53>, rg, dim3(RT), s, a.in, a.in_pitch, tmp, tmp_pitch, a.W, a.H);
-        if (e == hipSuccess) e = launch(k_cols_forward<CDF53>, cg, dim3(RT), s, ct, tmp_pitch, a);
+        if (e == hipSuccess) e = launch(k_cols_forward<CDF53>, cg, dim3(RT), s, ct, tmp_pitch, a, cseg);
     } else if (wavelet == CDF97) {
         e = launch(k_rows_forward<CDF97>, rg, dim3(RT), s, a.in, a.in_pitch, tmp, tmp_pitch, a.W, a.H);
-        if (e == hipSuccess) e = launch(k_cols_forward<CDF97>, cg, dim3(RT), s, ct, tmp_pitch, a);
+        if (e == hipSuccess) e = launch(k_cols_forward<CDF97>, cg, dim3(RT), s, ct, tmp_pitch, a, cseg);
     }
     return e;
 }
@@ -235,16 +252,17 @@ hipError_t launch_rowcol_inverse(int wavelet, const InvArgs &a, float *tmp, ptrd
 {
     const int K = wavelet == CDF97 ? 2 : 1;
     const int QW = (a.W + 1) / 2, QH = (a.H + 1) / 2;
+    const int cseg = col_segment(a.W, QH);
     const dim3 rg((QW + NPW - 2 * K - 1) / (NPW - 2 * K), (a.H + RW - 1) / RW);
-    const dim3 cg((a.W + RT - 1) / RT, (QH + CSEG - 1) / CSEG);
+    const dim3 cg((a.W + RT - 1) / RT, (QH + cseg - 1) / cseg);
     hipError_t e = hipErrorInvalidValue;
     const float *ct = tmp;
     if (wavelet == CDF53) {
-        e = launch(k_cols_inverse<CDF53>, cg, dim3(RT), s, a, tmp, tmp_pitch);
+        e = launch(k_cols_inverse<CDF53>, cg, dim3(RT), s, a, tmp, tmp_pitch, cseg);
         if (e == hipSuccess)
             e = launch(k_rows_inverse<CDF53>, rg, dim3(RT), s, ct, tmp_pitch, a.out, a.out_pitch, a.W, a.H);
     } else if (wavelet == CDF97) {
-        e = launch(k_cols_inverse<CDF97>, cg, dim3(RT), s, a, tmp, tmp_pitch);
+        e = launch(k_cols_inverse<CDF97>, cg, dim3(RT), s, a, tmp, tmp_pitch, cseg);
         if (e == hipSuccess)
             e = launch(k_rows_inverse<CDF97>, rg, dim3(RT), s, ct, tmp_pitch, a.out, a.out_pitch, a.W, a.H);
     }

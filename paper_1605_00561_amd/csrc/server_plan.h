@@ -92,9 +92,9 @@ public:
 };
 
 // One pending request as the scheduler sees it: the byte ranges it reads and
-// writes, its direction and depth, the bytes of its own LL buffers in a
-// batched call's workspace, and its HBM footprint (the bytes of its input,
-// its output and its LL buffers).
+// writes, its direction and depth, the bytes of its own part of a batched
+// call's workspace (its LL buffers and tile-index entries), and its HBM
+// footprint (the bytes of its input, its output and that part).
 struct Item {
     uintptr_t src_lo, src_hi, dst_lo, dst_hi;
     int inverse, levels;
@@ -102,13 +102,13 @@ struct Item {
     size_t footprint;
 };
 
-// HBM footprint of a request: input span + output span + LL buffers.
+// HBM footprint of a request: input span + output span + workspace part.
 inline size_t footprint_of(const Item &it)
 {
     return (size_t)(it.src_hi - it.src_lo) + (size_t)(it.dst_hi - it.dst_lo) + it.ll_bytes;
 }
 
-// Workspace of one direction's batched call: table + the images' LL buffers.
+// Workspace of one direction's batched call: tables + the images' own parts.
 struct Group {
     int count = 0, lmax = 0;
     size_t ll = 0;

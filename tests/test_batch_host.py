@@ -40,7 +40,13 @@ def test_workspace_bytes_is_table_plus_each_images_ll_buffers():
                                 ("cdf53", 6, 999, 333)]]
     lmax = 6
     rows_table = _al(((n + 3) // 4 * 4) * lmax)  # one byte per image and level, rows of 4k bytes
-    assert ws_bytes(a, n) == _al(64 * n) + _al(4 * lmax * (n + 1)) + rows_table + sum(per)
+    # tile-image index: two bytes per tile, every level at the wavelet's shortest height
+    bound = 0
+    for (wav, lev, w, h) in [("cdf97", 3, 1000, 700), ("cdf53", 1, 64, 64), ("cdf53", 6, 999, 333)]:
+        for _ in range(lev):
+            bound += tiles(wav, min(dwt2.TILE_ROWS[wav]), w, h)
+            w, h = (w + 1) // 2, (h + 1) // 2
+    assert ws_bytes(a, n) == _al(64 * n) + _al(4 * lmax * (n + 1)) + rows_table + _al(2 * bound) + sum(per)
     assert ws_bytes(a, 0) == 0
     # arithmetic and norm do not change the layout
     assert ws_bytes(a, n, arithmetic="fp64", norm="paper") == ws_bytes(a, n)
