@@ -623,8 +623,10 @@ def batch_table(dwt2, torch, workloads, reps):
     out["per_image_forward"] = row(_times_us(torch, lambda: loop(False), reps))
     out["per_image_inverse"] = row(_times_us(torch, lambda: loop(True), reps))
     lmax = max(levs)
+    rows_words = lmax * ((n + 3) // 4 * 4) // 4  # the tile-height table, one byte per image and level
     out["launches_per_direction"] = {
-        "batched": -(-16 * n // 768) - (-lmax * (n + 1) // 768) + lmax,  # table copies + levels
+        # record, tile-start and tile-height copies, the tile-image index, the levels
+        "batched": -(-16 * n // 768) - (-lmax * (n + 1) // 768) - (-rows_words // 768) + 1 + lmax,
         "per_image": sum(levs)}
     torch.cuda.synchronize()
     rt = max(float((z - x).abs().max()) for x, z in zip(xs, zs))
