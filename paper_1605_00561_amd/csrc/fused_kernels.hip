@@ -400,6 +400,38 @@ __device__ __forceinline__ void inverse_tile(T (&q)[RB][4], const Planes<WAV, RB
 __device__ __forceinline__ void store1(float *p, float v) { *p = v; }
 __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)p = make_float2(a, b); }
 
+// Image and coefficient pointers as global-memory pointers.  A pointer the
+// compiler cannot place in an address space (one read from device memory, as
+// in an image record of the batched launch) is accessed with flat
+// instructions, which count on the LDS counter too: every LDS wait in the
+// tile body then also waits for the tile's outstanding image loads and
+// stores.  The tile bodies therefore access images through pointers typed as
+// global (GM = true); the multi-level tail, whose LL bands are in LDS, keeps
+// generic pointers (GM = false).
+typedef __attribute__((address_space(1))) float gfloat;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) f32x2 gf32x2;
+template <bool GM>
+__device__ __forceinline__ auto mem(const float *p)
+{
+    if constexpr (GM) return (const gfloat *)p;
+    else return p;
+}
+template <bool GM>
+__device__ __forceinline__ auto mem(float *p)
+{
+    if constexpr (GM) return (gfloat *)p;
+    else return p;
+}
+__device__ __forceinline__ float2 load2(const float *p) { return *(const float2 *)p; }
+__device__ __forceinline__ float2 load2(const gfloat *p)
+{
+    const f32x2 v = *(const gf32x2 *)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void store1(gfloat *p, float v) { *p = v; }
+__device__ __forceinline__ void store2(gfloat *p, float a, float b) { *(gf32x2 *)p = f32x2{a, b}; }
+
 // Horizontal paths.  VEC: the tile's 128 pixel columns lie inside the image
 // and rows are 8-byte aligned (`aligned`), so each pixel-row pair is one
 // float2 per lane.  Otherwise (a tile at the left or right image edge) each
@@ -407,7 +439,7 @@ __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)
 // float2 when the rows are aligned, and only the lanes that hold mirrored or
 // dead columns load two samples from their mirrored positions.  The values
 // loaded, and so the results, are the same on every path.
-template <int WAV, int RB, typename T, bool VEC, int NB = 2>
+template <int WAV, int RB, typename T, bool VEC, int NB = 2, bool GM = true>
 __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int tr, int w, int lane,
                                          bool aligned)
 {
@@ -422,12 +454,23 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int t
     const int qr0 = tr * IY - HQ;  // quadruple row of tile row 0
 
     T q[RB][4];
+    // On the aligned edge path every lane loads a float2: a lane outside the
+    // image loads its row's first pair (every level is at least 2 wide, so
+    // the pair is in bounds), discards it and loads its two mirrored samples.
+    // The one unconditional float2 keeps the inside lanes' loads 8 bytes wide.
+    const int pc = lane_vec ? 2 * qc : 0;
     auto load = [&](int qr, float &ll, float &hl, float &lh, float &hh) {
-        const float *r0 = a.in + (ptrdiff_t)ws_mirror(2 * qr, H) * a.in_pitch;
-        const float *r1 = a.in + (ptrdiff_t)ws_mirror(2 * qr + 1, H) * a.in_pitch;
-        if (lane_vec) {
-            const float2 e = *(const float2 *)(r0 + 2 * qc), o = *(const float2 *)(r1 + 2 * qc);
+        const auto r0 = mem<GM>(a.in) + (ptrdiff_t)ws_mirror(2 * qr, H) * a.in_pitch;
+        const auto r1 = mem<GM>(a.in) + (ptrdiff_t)ws_mirror(2 * qr + 1, H) * a.in_pitch;
+        if constexpr (VEC) {
+            const float2 e = load2(r0 + 2 * qc), o = load2(r1 + 2 * qc);
             ll = e.x; hl = e.y; lh = o.x; hh = o.y;
+        } else if (aligned) {
+            const float2 e = load2(r0 + pc), o = load2(r1 + pc);
+            ll = e.x; hl = e.y; lh = o.x; hh = o.y;
+            if (!lane_vec) {
+                ll = r0[x0]; hl = r0[x1]; lh = r1[x0]; hh = r1[x1];
+            }
         } else {
             ll = r0[x0]; hl = r0[x1]; lh = r1[x0]; hh = r1[x1];
         }
@@ -456,12 +499,12 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int t
     for (int j = 0; j < RB; j++) {
         const int r = tile_row(j, w), qr = qr0 + r;
         if (r < HQ || r >= TY - HQ || qr >= QH) continue;
-        store1(a.ll + (ptrdiff_t)qr * a.ll_pitch + qc,
+        store1(mem<GM>(a.ll) + (ptrdiff_t)qr * a.ll_pitch + qc,
                  (float)(q[j][LL] * (T)a.s.ll + (T)cll));
-        float *drow = a.det + (ptrdiff_t)qr * a.det_pitch;
+        const auto drow = mem<GM>(a.det) + (ptrdiff_t)qr * a.det_pitch;
         if (qc < WH) store1(drow + QW + qc, (float)q[j][HL]);
         if (qr < HHr) {
-            float *hrow = a.det + (ptrdiff_t)(QH + qr) * a.det_pitch;
+            const auto hrow = mem<GM>(a.det) + (ptrdiff_t)(QH + qr) * a.det_pitch;
             store1(hrow + qc, (float)q[j][LH]);
             if (qc < WH) store1(hrow + QW + qc, (float)(q[j][HH] * (T)a.s.hh));
         }
@@ -473,7 +516,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int t
 // lane.  Otherwise every lane whose pixel pair lies inside the image still
 // stores it as one float2 when the rows are aligned; the last column of an
 // odd width is stored alone.
-template <int WAV, int RB, typename T, bool VEC, int NB = 2>
+template <int WAV, int RB, typename T, bool VEC, int NB = 2, bool GM = true>
 __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int tr, int w, int lane,
                                          bool aligned)
 {
@@ -493,9 +536,9 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int t
     for (int j = 0; j < RB; j++) {
         const int qr = qr0 + tile_row(j, w);
         const int rl = ws_mirror(2 * qr, H) >> 1, rh = ws_mirror(2 * qr + 1, H) >> 1;
-        const float *lrow = a.det + (ptrdiff_t)rl * a.det_pitch;
-        const float *hrow = a.det + (ptrdiff_t)(QH + rh) * a.det_pitch;
-        raw[j][LL] = a.ll[(ptrdiff_t)rl * a.ll_pitch + cl];
+        const auto lrow = mem<GM>(a.det) + (ptrdiff_t)rl * a.det_pitch;
+        const auto hrow = mem<GM>(a.det) + (ptrdiff_t)(QH + rh) * a.det_pitch;
+        raw[j][LL] = mem<GM>(a.ll)[(ptrdiff_t)rl * a.ll_pitch + cl];
         raw[j][HL] = lrow[QW + ch];
         raw[j][LH] = hrow[cl];
         raw[j][HH] = hrow[QW + ch];
@@ -503,7 +546,7 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int t
     float c;
     {
         const int rm = ws_mirror(2 * G::centre_row(tr), H) >> 1;
-        const float sum = wave_sum(a.ll[(ptrdiff_t)rm * a.ll_pitch + cl]);
+        const float sum = wave_sum(mem<GM>(a.ll)[(ptrdiff_t)rm * a.ll_pitch + cl]);
         c = rintf(sum * (1.0f / TX) / (a.ll_gain * a.quantum)) * a.quantum;
     }
     const float cll = c * a.ll_gain;
@@ -526,7 +569,7 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int t
     for (int j = 0; j < RB; j++) {
         const int r = tile_row(j, w), qr = qr0 + r;
         if (r < HQ || r >= TY - HQ || qr >= QH) continue;
-        float *o0 = a.out + (ptrdiff_t)(2 * qr) * a.out_pitch;
+        const auto o0 = mem<GM>(a.out) + (ptrdiff_t)(2 * qr) * a.out_pitch;
         const T cc = c;
         const float v0 = (float)(q[j][LL] + cc), v1 = (float)(q[j][HL] + cc);
         const float v2 = (float)(q[j][LH] + cc), v3 = (float)(q[j][HH] + cc);
@@ -661,9 +704,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_tail_forward(TailArgs t)
             const int tc = tile % ntx, tr = tile / ntx;
             const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
             if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
-                fwd_body<WAV, RB, float, true>(a, tail_lds, tc, tr, w, lane, true);
+                fwd_body<WAV, RB, float, true, 2, false>(a, tail_lds, tc, tr, w, lane, true);
             else
-                fwd_body<WAV, RB, float, false>(a, tail_lds, tc, tr, w, lane, aligned);
+                fwd_body<WAV, RB, float, false, 2, false>(a, tail_lds, tc, tr, w, lane, aligned);
         }
         __syncthreads();  // LL of level k is level k + 1's input
     }
@@ -699,9 +742,9 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_tail_inverse(TailArgs t)
             const int tc = tile % ntx, tr = tile / ntx;
             const int px_first = 2 * (tc * (TX - 2 * HQ) - HQ);
             if (aligned && px_first >= 0 && px_first + 2 * TX <= W)
-                inv_body<WAV, RB, float, true>(a, tail_lds, tc, tr, w, lane, true);
+                inv_body<WAV, RB, float, true, 2, false>(a, tail_lds, tc, tr, w, lane, true);
             else
-                inv_body<WAV, RB, float, false>(a, tail_lds, tc, tr, w, lane, aligned);
+                inv_body<WAV, RB, float, false, 2, false>(a, tail_lds, tc, tr, w, lane, aligned);
         }
         __syncthreads();  // level k's output is level k - 1's LL
     }
