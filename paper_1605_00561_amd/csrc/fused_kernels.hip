@@ -407,7 +407,8 @@ __device__ __forceinline__ void store2(float *p, float a, float b) { *(float2 *)
 // tile body then also waits for the tile's outstanding image loads and
 // stores.  The tile bodies therefore access images through pointers typed as
 // global (GM = true); the multi-level tail, whose LL bands are in LDS, keeps
-// generic pointers (GM = false).
+// generic pointers (GM = false).  The 8-byte accesses go through a clang
+// vector type: HIP's float2 is a class whose members take generic references.
 typedef __attribute__((address_space(1))) float gfloat;
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) f32x2 gf32x2;
