@@ -259,6 +259,7 @@ def main():
                    "image": "cosine gradient (period 512) + N(0, 8^2), clipped to [0, 255]",
                    "buffer_sets": NSETS},
         "device_warmup_steps": n_dev_warm,
+        "device": device_info(torch, lib),
         "roofline": roofline,
         "round_trip_max_abs": rt_err,
     }
@@ -292,6 +293,33 @@ def main():
         out["cpu_baseline"] = cpu_baseline(img, wav, lev, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
+
+
+# hipDeviceAttribute_t values of ROCm 7's hip_runtime_api.h.
+HIP_ATTR_CLOCK_RATE, HIP_ATTR_MEMORY_BUS_WIDTH, HIP_ATTR_MEMORY_CLOCK_RATE = 5, 59, 60
+
+
+def device_info(torch, lib):
+    """The device, its peak clocks and the software versions of the run."""
+    props = torch.cuda.get_device_properties(0)
+    info = {"name": props.name, "arch": props.gcnArchName, "compute_units": props.multi_processor_count,
+            "memory_GiB": round(props.total_memory / 2**30, 1), "torch": torch.__version__,
+            "torch_hip": torch.version.hip}
+    try:
+        info["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        info["rocm"] = None
+    get = lib.hipDeviceGetAttribute  # resolved in the HIP runtime the library links
+    get.argtypes, get.restype = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int], ctypes.c_int
+    for key, attr, scale in (("peak_engine_clock_MHz", HIP_ATTR_CLOCK_RATE, 1e-3),
+                             ("peak_memory_clock_MHz", HIP_ATTR_MEMORY_CLOCK_RATE, 1e-3),
+                             ("memory_bus_bits", HIP_ATTR_MEMORY_BUS_WIDTH, 1)):
+        v = ctypes.c_int(0)
+        info[key] = round(v.value * scale) if get(ctypes.byref(v), attr, 0) == 0 else None
+    rv = ctypes.c_int(0)
+    lib.hipRuntimeGetVersion.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    info["hip_runtime"] = rv.value if lib.hipRuntimeGetVersion(ctypes.byref(rv)) == 0 else None
+    return info
 
 
 def tile_table(dwt2, torch, x, y, z, reps, sizes=(8192, 2048, 512)):
