@@ -1,6 +1,7 @@
 /*
  * dwt2.h -- C ABI of libdwt2: 2-D forward and inverse discrete wavelet
- * transform by CDF 5/3 and CDF 9/7 lifting on AMD MI355X (gfx950).
+ * transform by CDF 5/3, CDF 9/7 and Deslauriers-Dubuc 13/7 lifting on AMD
+ * MI355X (gfx950).
  *
  * Method: D. Barina, M. Kula, P. Zemcik, "Parallel Wavelet Schemes for
  * Images".  One level of the 2-D transform maps each quadruple of input
@@ -268,10 +269,10 @@ int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int height,
  * dwt2_workspace_bytes() exceeds DWT2_NOALLOC_SCRATCH_BYTES returns
  * DWT2_E_WORKSPACE and enqueues nothing (one-level calls need no workspace,
  * so any size works; two levels up to 8192 x 8192; deeper ones up to about
- * 50 Mpixel, e.g. 7000 x 7000).  Every call on a device shares that device's array: calls
- * that overlap in time on one device (on different streams, or from threads
- * whose streams are not ordered) race on it and give wrong results; calls
- * ordered on one stream do not.  The array needs no clearing: every call
+ * 50 Mpixel, e.g. 7000 x 7000).  Every call on a device shares that
+ * device's array: calls that overlap in time on one device (on different
+ * streams, or from threads whose streams are not ordered) race on it and
+ * give wrong results; calls ordered on one stream do not.  The array needs no clearing: every call
  * writes the workspace before reading it.  Statuses as dwt2_forward.
  */
 #define DWT2_NOALLOC_SCRATCH_BYTES 67108864 /* 64 MiB */
@@ -377,9 +378,10 @@ int dwt2_batch_tile_rows(int inverse, const dwt2_image *images, int count,
  * is carved from the caller's device arena, and a request waits while the
  * arena is full; with max_footprint_mib set, a request also waits while the
  * requests in flight plus it would touch more than that many bytes of device
- * memory, counting each request's input and output spans and its LL buffers.  A completion thread retires finished batches (in stream
- * order) and records each request's latency (submission to observed
- * completion, host clock).
+ * memory, counting each request's input and output spans and its LL
+ * buffers.  A completion thread retires finished batches (in stream order)
+ * and records each request's latency (submission to observed completion,
+ * host clock).
  *
  * Ordering: requests whose buffers overlap (one writes what another reads or
  * writes) never share a batch, and batches run in submission order on the
@@ -478,9 +480,9 @@ int dwt2_server_destroy(dwt2_server *server);
  * shared by the process (entries are replaced; the table holds at most 4096
  * entries, further sizes are not recorded).  Later FP32 calls with
  * tile_rows == 0 (tile_order == AUTO) use the recorded height (order) of a
- * level of that exact size, and batched calls the recorded height.  The call creates and
- * destroys a stream, two events and the graphs; it allocates no device
- * memory of its own.
+ * level of that exact size, and batched calls the recorded height.  The
+ * call creates and destroys a stream, two events and the graphs; it
+ * allocates no device memory of its own.
  * Argument rules are those of dwt2_forward; the scheme must be AUTO or
  * MONOLITHIC_STAR, the arithmetic AUTO or FP32, tile_rows, lds_buffers and
  * tile_order 0, else DWT2_E_UNSUPPORTED; repeats must be in [1, 1000], else
