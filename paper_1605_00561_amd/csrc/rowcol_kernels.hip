@@ -48,7 +48,7 @@ __global__ __launch_bounds__(RT) void k_rows_forward(const float *in, ptrdiff_t 
 {
     using L = Lift<WAV>;
     constexpr int K = L::K, OUTP = NPW - 2 * K;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
     const int row = blockIdx.y * RW + wv;
     if (row >= H) return;
     const int QW = (W + 1) >> 1, WH = W >> 1;
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(RT) void k_rows_inverse(const float *tmp, ptrdiff_t
 {
     using L = Lift<WAV>;
     constexpr int K = L::K, OUTP = NPW - 2 * K;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
     const int row = blockIdx.y * RW + wv;
     if (row >= H) return;
     const int QW = (W + 1) >> 1;

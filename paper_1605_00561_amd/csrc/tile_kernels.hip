@@ -668,7 +668,7 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_forward(FwdArgs a, int ntx, i
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;
     poison_lds(lds, lds_planes<SCH>() * PSZ);
-    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+    const int lane = threadIdx.x & (TX - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / TX);  // wavefront-uniform
     const int tc = tile % ntx, tr = tile / ntx;
     const int W = a.W, H = a.H;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1, WH = W >> 1, HH_ = H >> 1;
@@ -728,7 +728,7 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_inverse(InvArgs a, int ntx, i
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;
     poison_lds(lds, lds_planes<SCH>() * PSZ);
-    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+    const int lane = threadIdx.x & (TX - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / TX);  // wavefront-uniform
     const int tc = tile % ntx, tr = tile / ntx;
     const int W = a.W, H = a.H;
     const int QW = (W + 1) >> 1, QH = (H + 1) >> 1;
@@ -792,7 +792,7 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_none(NoneArgs a, int ntx, int
     __shared__ float lds[lds_planes<SCH>() * PSZ];
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;
-    const int lane = threadIdx.x & (TX - 1), wv = threadIdx.x / TX;
+    const int lane = threadIdx.x & (TX - 1), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / TX);  // wavefront-uniform
     const int tc = tile % ntx, tr = tile / ntx;
     const int qc = tc * IX - HQ + lane;
     Quads q;
