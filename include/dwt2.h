@@ -169,10 +169,10 @@ typedef DWT2_ENUM(dwt2_arith) { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_A
  * (1) overwrites one set of planes in place, adding a barrier between a step's
  * reads and the next publication (2 barriers per step, half the LDS).  Both
  * give bitwise identical results, with FP32 or FP64 lifting.  0 selects 2,
- * except for the FP64 forward transform, where it selects 1 (its
- * double-buffered planes would leave room for fewer work-groups per compute
- * unit).  Another value, or a nonzero value with another scheme or with the
- * batched calls returns DWT2_E_UNSUPPORTED.
+ * except with FP64 lifting, where it selects 1 (double-buffered FP64 planes
+ * would leave room for fewer work-groups per compute unit).  Another value,
+ * or a nonzero value with another scheme or with the batched calls returns
+ * DWT2_E_UNSUPPORTED.
  */
 
 /*

@@ -95,16 +95,15 @@ int parse(dwt2_wavelet wavelet, dwt2_ext ext, const dwt2_options *opt, Config *c
     return DWT2_OK;
 }
 
-// Default LDS buffering: double, except for the FP64 forward.  Its
-// double-buffered planes (36.9 KB at 9/7) would limit a CU to four
-// work-groups where its registers allow five (measured at 8192^2 9/7: 130 us
-// single against 138 double).  The FP64 inverse needs more registers and
-// fits four work-groups either way, so the extra barriers of single
-// buffering only cost it (139 us against 137).
-int buffers_of(const Config &c, bool inverse)
+// Default LDS buffering: double, except with FP64 lifting.  Double-buffered
+// FP64 planes (36.9 KB at 9/7) limit a CU to four work-groups, where the
+// registers (82 / 88 VGPRs forward / inverse) allow five; at 5/3 they limit it
+// to five where the registers allow eight.  Measured at 8192^2 9/7: forward
+// 124.6 us single against 131.0 double, inverse 123.7 against 131.7.
+int buffers_of(const Config &c)
 {
     if (c.lds_buffers) return c.lds_buffers;
-    return c.arithmetic == DWT2_ARITH_FP64 && !inverse ? 1 : 2;
+    return c.arithmetic == DWT2_ARITH_FP64 ? 1 : 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -448,7 +447,7 @@ DWT2_EXPORT int dwt2_forward(dwt2_wavelet wavelet, int levels, int width, int he
             e = dwt2::launch_rowcol_forward(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
             e = dwt2::launch_fused_forward(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
-                                           choose_rows(c.cfg, false, a.W, a.H), buffers_of(c.cfg, false),
+                                           choose_rows(c.cfg, false, a.W, a.H), buffers_of(c.cfg),
                                            choose_order(c.cfg, false, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_forward(c.cfg.wavelet, c.cfg.scheme, a, stream);
@@ -496,7 +495,7 @@ DWT2_EXPORT int dwt2_inverse(dwt2_wavelet wavelet, int levels, int width, int he
             e = dwt2::launch_rowcol_inverse(c.cfg.wavelet, a, tmp, a.W, stream);
         else if (c.cfg.scheme == DWT2_SCHEME_MONOLITHIC_STAR)
             e = dwt2::launch_fused_inverse(c.cfg.wavelet, c.cfg.arithmetic == DWT2_ARITH_FP64,
-                                           choose_rows(c.cfg, true, a.W, a.H), buffers_of(c.cfg, true),
+                                           choose_rows(c.cfg, true, a.W, a.H), buffers_of(c.cfg),
                                            choose_order(c.cfg, true, a.W, a.H), a, stream);
         else
             e = dwt2::launch_tile_inverse(c.cfg.wavelet, c.cfg.scheme, a, stream);
@@ -583,7 +582,7 @@ DWT2_EXPORT int dwt2_transform_only(int inverse, dwt2_wavelet wavelet, int width
     const bool inv = inverse != 0;
     const hipError_t e =
         c.scheme == DWT2_SCHEME_MONOLITHIC_STAR
-            ? dwt2::launch_fused_none(inv, c.wavelet, choose_rows(c, inv, width, height), buffers_of(c, inv),
+            ? dwt2::launch_fused_none(inv, c.wavelet, choose_rows(c, inv, width, height), buffers_of(c),
                                       choose_order(c, inv, width, height), a, stream)
             : dwt2::launch_tile_none(inv, c.wavelet, c.scheme, a, stream);
     return hip_status(e);
@@ -947,9 +946,9 @@ hipError_t capture_level(bool inverse, const Checked &c, const void *args, int r
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int i = 0; i < repeats && le == hipSuccess; i++)
-        le = inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg, inverse), order,
+        le = inverse ? dwt2::launch_fused_inverse(c.cfg.wavelet, false, rows, buffers_of(c.cfg), order,
                                                   *(const dwt2::InvArgs *)args, s)
-                     : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg, inverse), order,
+                     : dwt2::launch_fused_forward(c.cfg.wavelet, false, rows, buffers_of(c.cfg), order,
                                                   *(const dwt2::FwdArgs *)args, s);
     e = hipStreamEndCapture(s, g);  // always ends the capture
     if (le != hipSuccess) return le;
