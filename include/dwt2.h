@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define DWT2_VERSION 4
+#define DWT2_VERSION 5
 
 /*
  * The enums below have int as their underlying type in C++ as well as in C,
