@@ -97,32 +97,35 @@ constexpr bool built_rows(int rb)
 enum { LL = 0, HL = 1, LH = 2, HH = 3 };
 
 // DPP wave shifts: wave_shl:1 gives lane i the value of lane i+1, wave_shr:1
-// that of lane i-1; the end lane gets 0 (it holds a halo column).
+// that of lane i-1; the end lane gets 0 (it holds a halo column).  The zero
+// comes from the bound control (a lane with no source lane is written 0), not
+// from an "old" operand: an old value would need a register set to 0 before
+// every shift.
 constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
 __device__ __forceinline__ float from_right(float v)
 {
     return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_WAVE_SHL1, 0xf, 0xf, false));
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), DPP_WAVE_SHL1, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_left(float v)
 {
     return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), DPP_WAVE_SHR1, 0xf, 0xf, false));
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), DPP_WAVE_SHR1, 0xf, 0xf, true));
 }
 
 __device__ __forceinline__ double from_right(double v)
 {
     const int2 b = __builtin_bit_cast(int2, v);
     return __builtin_bit_cast(
-        double, make_int2(__builtin_amdgcn_update_dpp(0, b.x, DPP_WAVE_SHL1, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(0, b.y, DPP_WAVE_SHL1, 0xf, 0xf, false)));
+        double, make_int2(__builtin_amdgcn_mov_dpp(b.x, DPP_WAVE_SHL1, 0xf, 0xf, true),
+                          __builtin_amdgcn_mov_dpp(b.y, DPP_WAVE_SHL1, 0xf, 0xf, true)));
 }
 __device__ __forceinline__ double from_left(double v)
 {
     const int2 b = __builtin_bit_cast(int2, v);
     return __builtin_bit_cast(
-        double, make_int2(__builtin_amdgcn_update_dpp(0, b.x, DPP_WAVE_SHR1, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(0, b.y, DPP_WAVE_SHR1, 0xf, 0xf, false)));
+        double, make_int2(__builtin_amdgcn_mov_dpp(b.x, DPP_WAVE_SHR1, 0xf, 0xf, true),
+                          __builtin_amdgcn_mov_dpp(b.y, DPP_WAVE_SHR1, 0xf, 0xf, true)));
 }
 
 // Fused multiply-add in the arithmetic type of the kernel.
