@@ -198,31 +198,39 @@ __device__ __forceinline__ T lane_shift(T v)
 //   DD 13/7: P1 = {+1: -9/16, -1: 1/16, +2: 1/16}, U1 = {-1: 9/32, +1: -1/32, -2: -1/32}.
 // Lifting constants are in the arithmetic type: FP32 literals, or for FP64 the
 // same values written to double precision.
+// pp, uu: the diagonal coefficients of T_{P1} and S_{U1} for the one-tap CDF
+// operators (P1 P1* = p^2 z z*, U1 U1* = u^2 z^-1 z*^-1), rounded once.
 template <int WAV, typename T>
 struct Coef {
     __device__ static T p(int k) { return Lift<WAV>::p(k); }
     __device__ static T u(int k) { return Lift<WAV>::u(k); }
+    __device__ static T pp(int k) { return p(k) * p(k); }
+    __device__ static T uu(int k) { return u(k) * u(k); }
 };
 template <>
 struct Coef<CDF97, double> {
     __device__ static double p(int k) { return k == 0 ? -1.58613434205992355842832 : 0.88291107553093329591979; }
     __device__ static double u(int k) { return k == 0 ? -0.0529801185729614146241296 : 0.443506852043971152115604; }
+    __device__ static double pp(int k) { return p(k) * p(k); }
+    __device__ static double uu(int k) { return u(k) * u(k); }
 };
 
-// acc + sum_i tap_i * f(offset_i) over the predict (P1) or update (U1) taps.
-template <int WAV, bool PRED, typename T, typename F>
+// acc + sum_i tap_i * f(offset_i) over the predict (P1) or update (U1) taps
+// (NEG: acc - sum_i ...).
+template <int WAV, bool PRED, bool NEG = false, typename T, typename F>
 __device__ __forceinline__ T taps(T acc, int k, F f)
 {
+    constexpr T s = NEG ? (T)-1 : (T)1;
     if constexpr (WAV == DD137) {
         if constexpr (PRED)
-            return mad((T)0.0625, f.template get<2>(), mad((T)0.0625, f.template get<-1>(),
-                       mad((T)-0.5625, f.template get<1>(), acc)));
+            return mad(s * (T)0.0625, f.template get<2>(), mad(s * (T)0.0625, f.template get<-1>(),
+                       mad(s * (T)-0.5625, f.template get<1>(), acc)));
         else
-            return mad((T)-0.03125, f.template get<-2>(), mad((T)-0.03125, f.template get<1>(),
-                       mad((T)0.28125, f.template get<-1>(), acc)));
+            return mad(s * (T)-0.03125, f.template get<-2>(), mad(s * (T)-0.03125, f.template get<1>(),
+                       mad(s * (T)0.28125, f.template get<-1>(), acc)));
     } else {
-        if constexpr (PRED) return mad(Coef<WAV, T>::p(k), f.template get<1>(), acc);
-        else return mad(Coef<WAV, T>::u(k), f.template get<-1>(), acc);
+        if constexpr (PRED) return mad(s * Coef<WAV, T>::p(k), f.template get<1>(), acc);
+        else return mad(s * Coef<WAV, T>::u(k), f.template get<-1>(), acc);
     }
 }
 
@@ -245,8 +253,10 @@ struct Down {
 // Neighbour part of a predict step, T_{P1} (inverse: T_{-P1}), on every row:
 //   HL += P1 LL;  LH += P1* LL;  HH += P1 P1* LL + P1* HL + P1 LH
 // with P1 horizontal (across lanes, by DPP) and P1* vertical (rows of plane
-// buffer 0, published before the barrier); P1 P1* LL is P1 applied to the
-// vertical sum.  All reads are of pre-step values.  The inverse reads the
+// buffer 0, published before the barrier).  Every term is one multiply-add
+// into its accumulator; for the one-tap CDF operators P1 P1* LL is the
+// diagonal sample times p^2, for DD 13/7 P1 applied to the vertical sum
+// P1* LL.  All reads are of pre-step values.  The inverse reads the
 // post-step values and subtracts, except the P1 P1* term, which keeps its sign.
 template <int WAV, bool INV, int RB, typename T, int NB>
 __device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, RB, T, NB> &pl, int w, int lane, int k)
@@ -254,46 +264,71 @@ __device__ __forceinline__ void predict_step(T (&q)[RB][4], const Planes<WAV, RB
 #pragma unroll
     for (int j = 0; j < RB; j++) {
         const int r = tile_row(j, w);
-        const T vll = taps<WAV, true>((T)0, k, Down<WAV, RB, T, NB>{pl, 0, 0, r, lane});
-        const T vhl = taps<WAV, true>((T)0, k, Down<WAV, RB, T, NB>{pl, 0, 1, r, lane});
-        const T hll = taps<WAV, true>((T)0, k, Across<T>{q[j][LL]});
-        const T hlh = taps<WAV, true>((T)0, k, Across<T>{q[j][LH]});
-        const T dll = taps<WAV, true>((T)0, k, Across<T>{vll});
-        if (!INV) {
-            q[j][HL] += hll;
-            q[j][LH] += vll;
-            q[j][HH] += dll + (vhl + hlh);
+        const Down<WAV, RB, T, NB> below_ll{pl, 0, 0, r, lane}, below_hl{pl, 0, 1, r, lane};
+        T hh = q[j][HH];
+        if constexpr (WAV == DD137) {
+            const T vll = taps<WAV, true>((T)0, k, below_ll);
+            if (!INV) {
+                hh = taps<WAV, true>(hh, k, Across<T>{q[j][LH]});
+                hh = taps<WAV, true>(hh, k, below_hl);
+                hh = taps<WAV, true>(hh, k, Across<T>{vll});
+                q[j][LH] += vll;
+            } else {
+                hh = taps<WAV, true>(hh, k, Across<T>{vll});
+                hh = taps<WAV, true, true>(hh, k, below_hl);
+                hh = taps<WAV, true, true>(hh, k, Across<T>{q[j][LH]});
+                q[j][LH] -= vll;
+            }
         } else {
-            q[j][HL] -= hll;
-            q[j][LH] -= vll;
-            q[j][HH] += dll - (vhl + hlh);
+            const T p = INV ? -Coef<WAV, T>::p(k) : Coef<WAV, T>::p(k);
+            const T llb = below_ll.template get<1>();
+            hh = mad(p, from_right(q[j][LH]), hh);
+            hh = mad(p, below_hl.template get<1>(), hh);
+            hh = mad(Coef<WAV, T>::pp(k), from_right(llb), hh);
+            q[j][LH] = mad(p, llb, q[j][LH]);
         }
+        q[j][HH] = hh;
+        q[j][HL] = INV ? taps<WAV, true, true>(q[j][HL], k, Across<T>{q[j][LL]})
+                       : taps<WAV, true>(q[j][HL], k, Across<T>{q[j][LL]});
     }
 }
 
 // Neighbour part of an update step, S_{U1} (inverse: S_{-U1}), on every row:
 //   LL += U1 HL + U1* LH + U1 U1* HH;  HL += U1* HH;  LH += U1 HH
-// with the rows of plane buffer 1.
+// with the rows of plane buffer 1, each term one multiply-add as in the
+// predict step (CDF: U1 U1* HH is the diagonal sample times u^2).
 template <int WAV, bool INV, int RB, typename T, int NB>
 __device__ __forceinline__ void update_step(T (&q)[RB][4], const Planes<WAV, RB, T, NB> &pl, int w, int lane, int k)
 {
 #pragma unroll
     for (int j = 0; j < RB; j++) {
         const int r = tile_row(j, w);
-        const T vlh = taps<WAV, false>((T)0, k, Down<WAV, RB, T, NB>{pl, 1, 0, r, lane});
-        const T vhh = taps<WAV, false>((T)0, k, Down<WAV, RB, T, NB>{pl, 1, 1, r, lane});
-        const T hhl = taps<WAV, false>((T)0, k, Across<T>{q[j][HL]});
-        const T hhh = taps<WAV, false>((T)0, k, Across<T>{q[j][HH]});
-        const T dhh = taps<WAV, false>((T)0, k, Across<T>{vhh});
-        if (!INV) {
-            q[j][LL] += dhh + (hhl + vlh);
-            q[j][HL] += vhh;
-            q[j][LH] += hhh;
+        const Down<WAV, RB, T, NB> above_lh{pl, 1, 0, r, lane}, above_hh{pl, 1, 1, r, lane};
+        T ll = q[j][LL];
+        if constexpr (WAV == DD137) {
+            const T vhh = taps<WAV, false>((T)0, k, above_hh);
+            if (!INV) {
+                ll = taps<WAV, false>(ll, k, Across<T>{q[j][HL]});
+                ll = taps<WAV, false>(ll, k, above_lh);
+                ll = taps<WAV, false>(ll, k, Across<T>{vhh});
+                q[j][HL] += vhh;
+            } else {
+                ll = taps<WAV, false>(ll, k, Across<T>{vhh});
+                ll = taps<WAV, false, true>(ll, k, Across<T>{q[j][HL]});
+                ll = taps<WAV, false, true>(ll, k, above_lh);
+                q[j][HL] -= vhh;
+            }
         } else {
-            q[j][LL] += dhh - (hhl + vlh);
-            q[j][HL] -= vhh;
-            q[j][LH] -= hhh;
+            const T u = INV ? -Coef<WAV, T>::u(k) : Coef<WAV, T>::u(k);
+            const T hha = above_hh.template get<-1>();
+            ll = mad(u, from_left(q[j][HL]), ll);
+            ll = mad(u, above_lh.template get<-1>(), ll);
+            ll = mad(Coef<WAV, T>::uu(k), from_left(hha), ll);
+            q[j][HL] = mad(u, hha, q[j][HL]);
         }
+        q[j][LL] = ll;
+        q[j][LH] = INV ? taps<WAV, false, true>(q[j][LH], k, Across<T>{q[j][HH]})
+                       : taps<WAV, false>(q[j][LH], k, Across<T>{q[j][HH]});
     }
 }
 
