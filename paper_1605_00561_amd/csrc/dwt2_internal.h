@@ -71,6 +71,13 @@ struct Scale {
 // kernels' 8-byte vector accesses apply whatever the width.
 __host__ __device__ __forceinline__ ptrdiff_t ll_pitch(int w) { return ((ptrdiff_t)w + 63) & ~(ptrdiff_t)63; }
 
+// 1 / x for a normal power of two x, exactly: the exponent field reflected
+// about that of 1.  Dividing by x and multiplying by this give the same bits.
+__host__ __device__ __forceinline__ float recip_pow2(float x)
+{
+    return __builtin_bit_cast(float, 0x7F000000u - __builtin_bit_cast(unsigned, x));
+}
+
 // Whole-sample symmetric extension: index j -> [0, n), period 2(n-1), n >= 2.
 __host__ __device__ __forceinline__ int ws_mirror(int j, int n)
 {

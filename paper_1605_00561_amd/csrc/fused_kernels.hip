@@ -531,7 +531,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs &a, T *lds, int tc, int t
         float a0, a1, a2, a3;
         load(G::centre_row(tr), a0, a1, a2, a3);
         const float sum = wave_sum((a0 + a1) + (a2 + a3));
-        c = rintf(sum * (1.0f / (4 * TX)) / a.quantum) * a.quantum;
+        c = rintf(sum * (1.0f / (4 * TX)) * recip_pow2(a.quantum)) * a.quantum;
     }
 #pragma unroll
     for (int j = 0; j < RB; j++)
@@ -594,7 +594,7 @@ __device__ __forceinline__ void inv_body(const InvArgs &a, T *lds, int tc, int t
     {
         const int rm = ws_mirror(2 * G::centre_row(tr), H) >> 1;
         const float sum = wave_sum(mem<GM>(a.ll)[(ptrdiff_t)rm * a.ll_pitch + cl]);
-        c = rintf(sum * (1.0f / TX) / (a.ll_gain * a.quantum)) * a.quantum;
+        c = rintf(sum * (1.0f / TX) * recip_pow2(a.ll_gain * a.quantum)) * a.quantum;
     }
     const float cll = c * a.ll_gain;
 

@@ -693,7 +693,7 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_forward(FwdArgs a, int ntx, i
         const float *m0 = a.in + (ptrdiff_t)ws_mirror(2 * qm, H) * a.in_pitch;
         const float *m1 = a.in + (ptrdiff_t)ws_mirror(2 * qm + 1, H) * a.in_pitch;
         const float sum = wave_sum((m0[x0] + m0[x1]) + (m1[x0] + m1[x1]));
-        c = rintf(sum * (1.0f / (4 * TX)) / a.quantum) * a.quantum;
+        c = rintf(sum * (1.0f / (4 * TX)) * recip_pow2(a.quantum)) * a.quantum;
     }
 #pragma unroll
     for (int j = 0; j < NJ; j++)
@@ -743,7 +743,7 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_inverse(InvArgs a, int ntx, i
         const int qm = tr * IY - HQ + TY / 2;
         const int rm = ws_mirror(2 * qm, H) >> 1;
         const float sum = wave_sum(a.ll[(ptrdiff_t)rm * a.ll_pitch + cl]);
-        c = rintf(sum * (1.0f / TX) / (a.ll_gain * a.quantum)) * a.quantum;
+        c = rintf(sum * (1.0f / TX) * recip_pow2(a.ll_gain * a.quantum)) * a.quantum;
     }
     const float cll = c * a.ll_gain;
 
