@@ -188,18 +188,20 @@ def main():
               dwt2.EXT_WHOLE_SYMMETRIC, ctypes.byref(opt), None, 0, hs) for k in range(NSETS)]
     status = []
 
-    timer = HipTimer(3 * args.steps)
+    # Events 2i and 2i + 1 bracket step i's forward, 2i + 1 and 2i + 2 its
+    # inverse: a step's closing event is the next step's opening one.
+    timer = HipTimer(2 * args.steps + 1)
 
     def step(i, timed=False):
         k = i % NSETS
-        if timed:
-            timer.record(3 * i, hs)
+        if timed and i == 0:
+            timer.record(0, hs)
         status.append(lib.dwt2_forward(*fargs[k]))
         if timed:
-            timer.record(3 * i + 1, hs)
+            timer.record(2 * i + 1, hs)
         status.append(lib.dwt2_inverse(*iargs[k]))
         if timed:
-            timer.record(3 * i + 2, hs)
+            timer.record(2 * i + 2, hs)
 
     # Device warm-up: the kernels run ~10% slower over the first ~100 launches
     # of a process (measured), so untimed steps run for at least
@@ -224,8 +226,8 @@ def main():
     if any(st != dwt2.OK for st in status):
         raise dwt2.Dwt2Error(next(st for st in status if st != dwt2.OK), "timed step")
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    fwd_ms = [timer.ms(3 * i, 3 * i + 1) for i in range(args.steps)]
-    inv_ms = [timer.ms(3 * i + 1, 3 * i + 2) for i in range(args.steps)]
+    fwd_ms = [timer.ms(2 * i, 2 * i + 1) for i in range(args.steps)]
+    inv_ms = [timer.ms(2 * i + 1, 2 * i + 2) for i in range(args.steps)]
     timer.close()
     value = 2 * npx / (ms_per_step * 1e-3) / 1e9
 
