@@ -155,7 +155,8 @@ typedef DWT2_ENUM(dwt2_arith) { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_A
  * band of rows that contains its outputs), so the choice changes speed only.
  * 0 selects per level: the entry dwt2_autotune recorded for this wavelet,
  * direction and level size, else the tallest height that still gives at
- * least 1024 tiles (four per compute unit), else the shortest.  Another
+ * least the wavelet's fill threshold of tiles (5/3: 256, 9/7: 512, DD 13/7:
+ * 1536), else the shortest.  Another
  * value, or a nonzero value with another scheme or with the batched calls,
  * returns DWT2_E_UNSUPPORTED.
  */
@@ -352,11 +353,11 @@ int dwt2_inverse_batch(const dwt2_image *images, int count, dwt2_ext ext,
  * Tile heights of a batched call.  Each image's level runs at the height
  * dwt2_autotune recorded for its wavelet, direction and level size (FP32
  * lifting), else at its wavelet's tallest built height; when the level
- * launch would then have fewer than 1024 work-groups (four per compute
- * unit), the untuned images step down to shorter heights together until it
- * has, as far as the built heights go (the rule of dwt2_options.tile_rows,
- * applied to the launch instead of one image).  FP64 lifting runs at its one
- * height.  Heights change speed only, never the result.  Writes
+ * launch would then have fewer work-groups than the largest fill threshold
+ * among the untuned images' wavelets, those images step down to shorter
+ * heights together until it has, as far as the built heights go (the rule
+ * of dwt2_options.tile_rows, applied to the launch instead of one image).
+ * FP64 lifting runs at its one height.  Heights change speed only, never the result.  Writes
  * rows[0..count) for level `level` (0-based) of the forward (inverse == 0) or
  * inverse call with these arguments: an image's height, or 0 when it has no
  * such level.  Statuses as dwt2_batch_workspace_bytes; level < 0 or a null

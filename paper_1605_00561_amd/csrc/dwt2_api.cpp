@@ -116,10 +116,16 @@ struct TuneVal {
     int rows, order;
 };
 constexpr size_t kTuneMax = 4096;
-// Four work-groups per compute unit (256 CUs): below this a level is short
-// of work-groups and shorter tiles win; above it taller tiles (fewer halo
-// rows re-read) win, as measured over 512^2 .. 8192^2 levels.
-constexpr long long kFillTiles = 1024;
+// Fill thresholds per wavelet (5/3, 9/7, DD 13/7): a level takes the tallest
+// built height that gives it at least this many tiles.  Below it a level is
+// short of work-groups and a shorter tile wins; above it the taller tile
+// (fewer halo rows re-read, fewer work-groups to schedule) wins.  Fitted to
+// one-level device times of every built height at 14 level sizes from 512^2
+// to 16384^2 (square, 1920 x 1080, 3840 x 2160, 7680 x 4320): the choice is
+// then within 0.25 % of the fastest height on average, 4.6 % at worst (one
+// shared threshold of 1024 tiles: 0.8 %, 9 %).  DD 13/7's tall tile holds
+// twice the rows of its short one, hence its higher threshold.
+constexpr long long kFillTiles[3] = {256, 512, 1536};
 
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -129,7 +135,7 @@ int rule_rows(int wavelet, int W, int H)
 {
     int pick = dwt2::kFusedRows[wavelet][0];  // heights are listed in ascending order
     for (int r : dwt2::kFusedRows[wavelet])
-        if (r > 0 && dwt2::fused_tile_count(wavelet, r, W, H) >= kFillTiles) pick = r;
+        if (r > 0 && dwt2::fused_tile_count(wavelet, r, W, H) >= kFillTiles[wavelet]) pick = r;
     return pick;
 }
 
@@ -640,10 +646,11 @@ struct BatchPlan {
 // Tile heights of batched level k.  An image level whose size dwt2_autotune
 // recorded takes the recorded height (FP32 lifting).  The others take, per
 // wavelet, the tallest built height, or a shorter one when the launch would
-// otherwise have fewer than kFillTiles work-groups: step s takes the s-th
-// height down from the tallest (the shortest when a wavelet has fewer), and
-// the launch uses the smallest step that reaches kFillTiles (else the
-// largest), as the single-image rule does for one image.  FP64 lifting is
+// otherwise have fewer work-groups than the largest fill threshold among
+// their wavelets: step s takes the s-th height down from the tallest (the
+// shortest when a wavelet has fewer), and the launch uses the smallest step
+// that reaches that threshold (else the largest), as the single-image rule
+// does for one image.  FP64 lifting is
 // built at one height per wavelet.  Fills rows[i] (0 without level k) and
 // returns the launch's tile count.
 long long batch_level_rows(const BatchPlan &p, bool inverse, int k, unsigned char *rows)
@@ -661,6 +668,7 @@ long long batch_level_rows(const BatchPlan &p, bool inverse, int k, unsigned cha
     };
     std::vector<int> tuned_rows(count, 0);
     long long fixed = 0;  // tiles of images whose height does not depend on the step
+    long long fill = 0;   // the launch's fill threshold
     for (int i = 0; i < count; i++) {
         const dwt2::BatchImage &r = p.rec[i];
         if (r.levels <= k) continue;
@@ -672,6 +680,7 @@ long long batch_level_rows(const BatchPlan &p, bool inverse, int k, unsigned cha
         if (fp64) tuned_rows[i] = dwt2::kFusedRowsFp64[r.wavelet];
         else if (tuned(c, inverse, w, h, &v)) tuned_rows[i] = v.rows;
         if (tuned_rows[i]) fixed += dwt2::fused_tile_count(r.wavelet, tuned_rows[i], w, h);
+        else fill = std::max(fill, kFillTiles[r.wavelet]);
     }
     constexpr int kSteps = dwt2::kFusedRowsMax;
     int step = kSteps - 1;
@@ -684,7 +693,7 @@ long long batch_level_rows(const BatchPlan &p, bool inverse, int k, unsigned cha
             level_wh(r, &w, &h);
             total += dwt2::fused_tile_count(r.wavelet, height_at(r.wavelet, st), w, h);
         }
-        if (total >= kFillTiles) {
+        if (total >= fill) {
             step = st;
             break;
         }

@@ -173,10 +173,15 @@ def tiles(wav, rows, w, h):
     return -(-((w + 1) // 2) // ix) * -(-((h + 1) // 2) // iy)
 
 
+# Fill thresholds (tiles) of the single-image height rule, per wavelet.
+FILL = {"cdf53": 256, "cdf97": 512, "dd137": 1536}
+
+
 def model_rows(entries, level, tuned=None, fp64=False):
     """The rule of dwt2_batch_tile_rows, written out: tuned sizes keep their
     height; the others step down together from the tallest height until the
-    launch has 1024 tiles."""
+    launch has as many tiles as the largest fill threshold of their
+    wavelets."""
     tuned = tuned or {}
     live = []
     for (wav, lev, w, h, *_ ) in entries:
@@ -196,9 +201,10 @@ def model_rows(entries, level, tuned=None, fp64=False):
     def pick(step):
         return [0 if e is None else tuned.get(e, height(e[0], step)) for e in live]
 
+    fill = max([FILL[e[0]] for e in live if e and e not in tuned], default=0)
     for step in range(3):
         rows = pick(step)
-        if sum(tiles(e[0], r, e[1], e[2]) for e, r in zip(live, rows) if e) >= 1024:
+        if sum(tiles(e[0], r, e[1], e[2]) for e, r in zip(live, rows) if e) >= fill:
             return rows
     return pick(2)
 
@@ -229,7 +235,7 @@ def test_batch_tile_rows_follow_the_launch_fill_rule():
 
 
 def test_batch_tile_rows_take_tuned_heights():
-    entries = [img("cdf97", 3, 2000, 1500), img("cdf53", 2, 2000, 1800, src=FAKE + 128 * MiB,
+    entries = [img("cdf97", 3, 2000, 1500), img("cdf53", 2, 800, 600, src=FAKE + 128 * MiB,
                                                   dst=FAKE + 192 * MiB)]
     a, n = images(*entries)
     try:
@@ -237,10 +243,10 @@ def test_batch_tile_rows_take_tuned_heights():
         st, rows = dwt2.dwt2_batch_tile_rows(0, a, n, 0)
         assert st == dwt2.OK and rows == [TALLEST["cdf97"], TALLEST["cdf53"]]
         # a forward entry for the 9/7 image's level 1 (1000 x 750) and an
-        # inverse one for the 5/3 image's level 1 (1000 x 900)
-        assert dwt2.dwt2_tune_import("1 0 1000 750 2 1\n0 1 1000 900 2 1\n") == dwt2.OK
+        # inverse one for the 5/3 image's level 1 (400 x 300)
+        assert dwt2.dwt2_tune_import("1 0 1000 750 2 1\n0 1 400 300 2 1\n") == dwt2.OK
         fwd = {("cdf97", 1000, 750): 2}
-        inv = {("cdf53", 1000, 900): 2}
+        inv = {("cdf53", 400, 300): 2}
         assert dwt2.dwt2_batch_tile_rows(0, a, n, 1)[1] == model_rows(entries, 1, fwd) == [2, 3]
         # the inverse launch of level 1 is short of work-groups: the untuned
         # 9/7 image steps down, the tuned 5/3 image keeps its height

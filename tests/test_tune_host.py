@@ -68,8 +68,11 @@ def tiles(wav, rows, w, h):
     return -(-qw // (64 - 2 * hq)) * -(-qh // (4 * rows - 2 * hq))
 
 
+FILL = {"cdf53": 256, "cdf97": 512, "dd137": 1536}
+
+
 def expected_rule(wav, w, h):
-    ok = [r for r in dwt2.TILE_ROWS[wav] if tiles(wav, r, w, h) >= 1024]
+    ok = [r for r in dwt2.TILE_ROWS[wav] if tiles(wav, r, w, h) >= FILL[wav]]
     return max(ok) if ok else min(dwt2.TILE_ROWS[wav])
 
 
@@ -87,8 +90,12 @@ def test_selection_rule():
     assert dwt2.tile_rows("cdf97", 2048, 2048) == 4
     assert dwt2.tile_rows("cdf97", 8192, 8192) == 4
     assert dwt2.tile_rows("cdf53", 8192, 8192) == 3
-    assert dwt2.tile_rows("cdf53", 1024, 1024) == 2
+    assert dwt2.tile_rows("cdf53", 1024, 1024) == 3
+    assert dwt2.tile_rows("cdf53", 512, 512) == 2
+    assert dwt2.tile_rows("cdf97", 1024, 1024) == 3
+    assert dwt2.tile_rows("cdf97", 1920, 1080) == 4
     assert dwt2.tile_rows("dd137", 1024, 1024) == 3
+    assert dwt2.tile_rows("dd137", 2048, 2048) == 3
     assert dwt2.tile_rows("dd137", 4096, 4096) == 6
 
 
