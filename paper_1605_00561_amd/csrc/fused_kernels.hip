@@ -698,9 +698,18 @@ __global__ __launch_bounds__(NTHREADS) void k_fused_none(NoneArgs a, int ntx, in
         for (int e = 0; e < 4; e++) q[j][e] = none_sample(qc, qr0 + tile_row(j, w), e);
     if constexpr (INV) inverse_tile(q, pl, w, lane);
     else forward_tile(q, pl, w, lane);
+    // The checksum takes the values the level kernel would store: interior
+    // rows and lanes.  Halo rows read plane rows no work-group writes, so
+    // their values depend on what earlier kernels left in LDS and could be
+    // anything, the key's NaN pattern included.
     float acc = 0.0f;
+    if (lane >= G::HQ && lane < TX - G::HQ) {
 #pragma unroll
-    for (int j = 0; j < RB; j++) acc += (q[j][LL] + q[j][HL]) + (q[j][LH] + q[j][HH]);
+        for (int j = 0; j < RB; j++) {
+            const int r = tile_row(j, w);
+            if (r >= G::HQ && r < G::TY - G::HQ) acc += (q[j][LL] + q[j][HL]) + (q[j][LH] + q[j][HH]);
+        }
+    }
     if (__float_as_uint(acc) == a.key) a.sink[0] = acc;
 }
 
@@ -974,8 +983,29 @@ Grid fused_grid(int W, int H, int order)
     return g;
 }
 
+// Work-groups per CU at large levels.  The FP32 level kernels fit eight
+// work-groups on a CU (the wave slots bound them); from 2^26 pixels on, six
+// run faster.  Such a launch then reserves kCapLds bytes of LDS per
+// work-group (its planes plus an unused remainder), so that six fill a CU's
+// 160 KiB and a seventh does not fit.  Measured (one level, us forward /
+// inverse, eight per CU against six): 9/7 16384^2 438 / 428 against 415 /
+// 417, 5/3 16384^2 430 / 411 against 409 / 401, 9/7 12288^2 248 / 243
+// against 237 / 235, 9/7 8192^2 101 / 106 against 101 / 104.  Below 2^26
+// pixels (4096^2, 3840 x 2160, 2048^2) six are 2-5 % slower, and so is the
+// batched launch, whose images are small; both keep eight.
+constexpr long long kCapPixels = 1LL << 26;
+constexpr size_t kCapLds = 26624;  // 6 x 26624 <= 160 KiB < 7 x 26624
+
+template <int WAV, int RB, int NB>
+size_t cap_lds(int W, int H)
+{
+    constexpr size_t own = sizeof(float) * Geo<WAV, RB>::template plane_elems<NB>();
+    return (long long)W * H >= kCapPixels && own < kCapLds ? kCapLds - own : 0;
+}
+
 // FP64 kernels are built at one height per wavelet, FP32 kernels at every
-// height; both single- and double-buffered.
+// height; both single- and double-buffered.  FP64 kernels are held to five
+// work-groups per CU or fewer by their registers and take no cap.
 template <int WAV, int RB>
 hipError_t fused_fwd(bool fp64, bool single, int order, const FwdArgs &a, hipStream_t s)
 {
@@ -986,8 +1016,10 @@ hipError_t fused_fwd(bool fp64, bool single, int order, const FwdArgs &a, hipStr
             return single ? launch(k_fused_forward<WAV, RB, double, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
                           : launch(k_fused_forward<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
     if (fp64) return hipErrorInvalidValue;
-    return single ? launch(k_fused_forward<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
-                  : launch(k_fused_forward<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
+    return single ? launch_lds(k_fused_forward<WAV, RB, float, 1>, grid, block, cap_lds<WAV, RB, 1>(a.W, a.H), s, a,
+                               g.ntx, g.ntiles, g.bands)
+                  : launch_lds(k_fused_forward<WAV, RB, float, 2>, grid, block, cap_lds<WAV, RB, 2>(a.W, a.H), s, a,
+                               g.ntx, g.ntiles, g.bands);
 }
 
 template <int WAV, int RB>
@@ -1000,8 +1032,10 @@ hipError_t fused_inv(bool fp64, bool single, int order, const InvArgs &a, hipStr
             return single ? launch(k_fused_inverse<WAV, RB, double, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
                           : launch(k_fused_inverse<WAV, RB, double, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
     if (fp64) return hipErrorInvalidValue;
-    return single ? launch(k_fused_inverse<WAV, RB, float, 1>, grid, block, s, a, g.ntx, g.ntiles, g.bands)
-                  : launch(k_fused_inverse<WAV, RB, float, 2>, grid, block, s, a, g.ntx, g.ntiles, g.bands);
+    return single ? launch_lds(k_fused_inverse<WAV, RB, float, 1>, grid, block, cap_lds<WAV, RB, 1>(a.W, a.H), s, a,
+                               g.ntx, g.ntiles, g.bands)
+                  : launch_lds(k_fused_inverse<WAV, RB, float, 2>, grid, block, cap_lds<WAV, RB, 2>(a.W, a.H), s, a,
+                               g.ntx, g.ntiles, g.bands);
 }
 
 template <int WAV, int RB>

@@ -803,9 +803,17 @@ __global__ __launch_bounds__(NTHREADS) void k_tile_none(NoneArgs a, int ntx, int
         for (int e = 0; e < 4; e++) q.v[j][e] = (float)((qc * 3 + qr * 5 + e * 7) & 255);
     }
     transform_tile<WAV, SCH, INV>(lds, q, lane, wv);
+    // The checksum takes the values the level kernel would store (interior
+    // rows and lanes); halo values may come from LDS cells no work-group
+    // writes.
     float acc = 0.0f;
+    if (lane >= HQ && lane < TX - HQ) {
 #pragma unroll
-    for (int j = 0; j < NJ; j++) acc += (q.v[j][LL] + q.v[j][HL]) + (q.v[j][LH] + q.v[j][HH]);
+        for (int j = 0; j < NJ; j++) {
+            const int r = j * NWAVES + wv;
+            if (r >= HQ && r < TY - HQ) acc += (q.v[j][LL] + q.v[j][HL]) + (q.v[j][LH] + q.v[j][HH]);
+        }
+    }
     if (__float_as_uint(acc) == a.key) a.sink[0] = acc;
 }
 
