@@ -1004,8 +1004,9 @@ size_t cap_lds(int W, int H)
 }
 
 // FP64 kernels are built at one height per wavelet, FP32 kernels at every
-// height; both single- and double-buffered.  FP64 kernels are held to five
-// work-groups per CU or fewer by their registers and take no cap.
+// height; both single- and double-buffered.  FP64 launches take no cap: the
+// 9/7 and DD 13/7 kernels are held to five work-groups per CU or fewer by
+// their registers, and the cap was not measured on the 5/3 one.
 template <int WAV, int RB>
 hipError_t fused_fwd(bool fp64, bool single, int order, const FwdArgs &a, hipStream_t s)
 {
