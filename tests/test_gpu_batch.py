@@ -195,3 +195,29 @@ def test_batch_at_tuned_and_stepped_down_heights():
         torch.cuda.synchronize()
         for j, i in enumerate(sub):
             assert torch.equal(ys[j], single(xs[i], wavs[i], levs[i], "unit_dc", "auto")), f"small {i}"
+
+
+def test_large_levels_single_calls_equal_batch():
+    """Single-image levels of 2^26 pixels and more run with six work-groups per
+    CU (LDS reserved per work-group); batched launches never do.  The
+    reservation changes where work-groups run, not what they compute: at a
+    ragged size just above the threshold both give the same bits, forward and
+    inverse, and the smallest image of the batch (whose levels are below the
+    threshold) stays pinned to the oracle."""
+    rng = np.random.default_rng(210)
+    w, h = 8203, 8193  # 67.2 M pixels >= 2^26; odd sides, ragged last tiles
+    assert w * h >= 1 << 26
+    x = rng.integers(0, 256, size=(h, w)).astype(np.float32)
+    small = rng.integers(0, 256, size=(300, 517)).astype(np.float32)
+    xs = [to_dev(x), to_dev(small)]
+    for wav in ("cdf97", "cdf53"):
+        wavs, levs = [wav, wav], [2, 2]
+        ys = dwt2.forward_batch(xs, wavs, levs, outs=outs_like(xs))
+        zs = dwt2.inverse_batch(ys, wavs, levs, outs=outs_like(xs))
+        y1 = single(xs[0], wav, 2, "unit_dc", "auto")
+        z1 = single(ys[0], wav, 2, "unit_dc", "auto", inverse=True)
+        assert torch.equal(ys[0], y1), wav
+        assert torch.equal(zs[0], z1), wav
+        check(to_host(ys[1]), oracle.forward(small.astype(np.float64), wav, 2), False, f"small {wav}")
+    del xs, ys, zs, y1, z1
+    torch.cuda.empty_cache()
