@@ -24,8 +24,10 @@
 //     visible.  Two plane buffers alternate between predict and update, so
 //     Monolithic* keeps its two barriers per lifting pair (double buffering;
 //     single buffering, NB = 1, adds one barrier per step, Sec. 6).
-// The per-level kernels use at most 29 KB of LDS (FP32), so occupancy is set
-// by registers; the multi-level tail adds its LL buffers, up to 60 KB.
+// The per-level kernels' planes take at most 29 KB of LDS (FP32), so
+// registers and wave slots set their occupancy, except that launches of
+// 2^26 pixels and up reserve 26 KB per work-group (six per CU, which runs
+// faster there); the multi-level tail adds its LL buffers, up to 60 KB.
 //
 // Borders: whole-sample symmetric extension, samples read from mirrored
 // positions.  Centring: each tile subtracts a rounded local mean c from its
