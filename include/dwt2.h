@@ -184,8 +184,8 @@ typedef DWT2_ENUM(dwt2_arith) { DWT2_ARITH_AUTO = 0, DWT2_ARITH_FP32 = 1, DWT2_A
  * the same rows at a time.  In both, most neighbouring tiles run on the same
  * XCD and share their halo in its L2.  Not in the paper; it changes speed
  * only, never the result.  AUTO selects per level: the entry
- * dwt2_autotune recorded, else BANDS for levels of at least 2^27 pixels and
- * 2048 pixels width, else RUNS.  A nonzero value with another scheme or with
+ * dwt2_autotune recorded, else BANDS for levels of at least 5 x 2^25
+ * pixels and 2048 pixels width, else RUNS.  A nonzero value with another scheme or with
  * the batched calls returns DWT2_E_UNSUPPORTED.
  */
 typedef DWT2_ENUM(dwt2_order) {

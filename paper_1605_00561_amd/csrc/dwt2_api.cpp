@@ -139,11 +139,14 @@ int rule_rows(int wavelet, int W, int H)
     return pick;
 }
 
-// Tile order rule: the band order from 2^27 pixels on, when the level is at
-// least 2048 pixels (16 or more tile columns, two per XCD) wide.  Measured
-// on 9/7 and 5/3 levels from 8192^2 to 16384^2: runs are faster up to about
-// 10240^2, bands from 12288^2 on (by 6-19 % in the forward direction).
-constexpr long long kBandPixels = 1LL << 27;
+// Tile order rule: the band order from 5 x 2^25 pixels (about 12953^2) on,
+// when the level is at least 2048 pixels (16 or more tile columns, two per
+// XCD) wide.  Measured with the launches' work-group cap (six per CU from
+// 2^26 pixels), 9/7 and 5/3, forward and inverse, summed, us runs against
+// bands: 12288^2 936 against 964, 12800^2 1023 against 1036, 13312^2 1132
+// against 1109, 13824^2 1229 against 1184, 14336^2 1337 against 1267,
+// 16384^2 1690 against 1646; at 8192^2 to 11264^2 runs lead by 3-7 %.
+constexpr long long kBandPixels = 5LL << 25;
 constexpr int kBandMinWidth = 2048;
 
 int rule_order(int W, int H)

@@ -268,16 +268,18 @@ def test_tile_order_option_validation():
 
 
 def test_tile_order_rule():
-    """Bands from 2^27 pixels on when the level is at least 2048 pixels wide."""
+    """Bands from 5 x 2^25 pixels on when the level is at least 2048 pixels wide."""
     for wav in ("cdf53", "cdf97", "dd137"):
         for inverse in (False, True):
             assert dwt2.tile_order(wav, 8192, 8192, inverse=inverse) == "runs"
             assert dwt2.tile_order(wav, 10240, 10240, inverse=inverse) == "runs"
-            assert dwt2.tile_order(wav, 16384, 8192, inverse=inverse) == "bands"   # exactly 2^27
-            assert dwt2.tile_order(wav, 16384, 8191, inverse=inverse) == "runs"
+            assert dwt2.tile_order(wav, 12288, 12288, inverse=inverse) == "runs"
+            assert dwt2.tile_order(wav, 16384, 10240, inverse=inverse) == "bands"  # exactly 5 x 2^25
+            assert dwt2.tile_order(wav, 16384, 10239, inverse=inverse) == "runs"
+            assert dwt2.tile_order(wav, 13312, 13312, inverse=inverse) == "bands"
             assert dwt2.tile_order(wav, 16384, 16384, inverse=inverse) == "bands"
-            assert dwt2.tile_order(wav, 2048, 65536, inverse=inverse) == "bands"
-            assert dwt2.tile_order(wav, 2047, 65600, inverse=inverse) == "runs"   # too narrow
+            assert dwt2.tile_order(wav, 2048, 81920, inverse=inverse) == "bands"
+            assert dwt2.tile_order(wav, 2047, 82000, inverse=inverse) == "runs"   # too narrow
             assert dwt2.tile_order(wav, 16384, 16384, arithmetic="fp64") == "bands"
     assert dwt2.tile_order("cdf97", 16384, 16384, order="runs") == "runs"      # explicit wins
     assert dwt2.tile_order("cdf97", 64, 64, order="bands") == "bands"
